@@ -1,0 +1,201 @@
+"""Benchmark: batched Newton power flow on one MI355X.
+
+Workload (default): synthetic 118-bus meshed grid (tree + 60 extra branches,
+53 PV, 64 PQ, slack bus 0), batch of 1024 load scenarios, tolerance 1e-8 pu,
+flat start.  One step runs the whole path on the batch, inputs resident in
+HBM: the plain FP64 Newton solve, the mixed-precision solve (FP32 LU
+refactorisation and solves, FP64 mismatch / convergence / update and two
+FP64-residual refinement steps), and one differentiable-layer forward +
+backward (mixed-precision solve keeping the factors + adjoint).  Each part is
+timed with HIP events on the stream the kernels run on.
+
+``value`` is the mixed-precision solves/s; the FP64 rate and the layer's
+fwd+bwd samples/s are reported beside it.  The roofline entry covers the
+dominant kernel (the mixed-precision Newton kernel): algorithmic bytes per
+launch (see the design doc for the byte model) over its measured average launch
+duration.  ``cpu_baseline`` times the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c1", help="grid name in gen.grids.SPECS")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def algorithmic_bytes_per_solve(n_bus, nnz_lu, iters, w, refine):
+    """Streaming byte model of one solve from flat start: 5 FP64 boundary
+    vectors, and per Newton iteration the LU values written once and read by
+    (1 + R) forward+backward solve passes plus (10 + 4R) FP64 state vectors."""
+    return 5 * n_bus * 8 + iters * (w * nnz_lu * (2 + refine) + (10 + 4 * refine) * n_bus * 8)
+
+
+def _oracle_worker(args):
+    name, batch, idx = args
+    from gen.grids import make_case
+    from oracle.newton import newton
+    from oracle.ybus import ybus_of
+    spec, net, sc = make_case(name, batch=batch)
+    Y = ybus_of(net)
+    t0 = time.perf_counter()
+    for b in idx:
+        newton(Y, net.bus_type, sc.pd[b], sc.qd[b], sc.pg[b], sc.vset[b], tol=spec.tol)
+    return len(idx), time.perf_counter() - t0
+
+
+def cpu_baseline(name, batch, budget_s):
+    """The oracle (dense FP64 Newton, one scenario per task) on the host's
+    cores, one BLAS thread per worker process."""
+    import multiprocessing as mp
+    import numpy as np
+    cores = len(os.sched_getaffinity(0))
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    ctx = mp.get_context("spawn")
+    # calibrate on a few scenarios, then size the sample to the time budget
+    n0, t0 = _oracle_worker((name, batch, list(range(min(8, batch)))))
+    per = t0 / max(n0, 1)
+    n = int(min(batch, max(cores, budget_s * cores / max(per, 1e-6))))
+    idx = np.unique(np.linspace(0, batch - 1, n).astype(int)).tolist()
+    chunks = [idx[i::cores] for i in range(cores) if idx[i::cores]]
+    t = time.perf_counter()
+    with ctx.Pool(len(chunks)) as pool:
+        res = pool.map(_oracle_worker, [(name, batch, c) for c in chunks])
+    wall = time.perf_counter() - t
+    solved = sum(r[0] for r in res)
+    # the workers' set-up (grid generation, Y_bus) is inside the wall time;
+    # report the solve-only rate from the workers' own clocks as well
+    solve_rate = solved / max(max(r[1] for r in res), 1e-9)
+    return {"value": solved / wall, "unit": "solves/s", "cores": len(chunks), "kind": "oracle",
+            "sample": f"{solved} of {batch} scenarios (every {max(1, batch // max(solved, 1))}th), "
+                      f"dense FP64 Newton + LAPACK, 1 BLAS thread per process",
+            "solve_only_value": solve_rate, "wall_s": wall}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported "
+                                   "(scenarios shard with no exchange; see DESIGN.md)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from gen.grids import SPECS, make_case
+    from paper_2606_07099_amd import PFTemplate, PFLayer
+
+    name = args.workload
+    spec, net, sc = make_case(name)
+    B = sc.batch
+    dev = torch.device("cuda:0")
+    d = {k: torch.as_tensor(getattr(sc, k), device=dev) for k in ("pd", "qd", "pg", "vset")}
+    t_build = time.perf_counter()
+    tpl64 = PFTemplate.from_network(net, B, tol=spec.tol, precision="fp64", keep_factors=False)
+    t_build = time.perf_counter() - t_build
+    tplmp = PFTemplate.from_network(net, B, tol=spec.tol, precision="mixed", keep_factors=False)
+    tpllay = PFTemplate.from_network(net, B, tol=spec.tol, precision="mixed", keep_factors=True)
+    layer = PFLayer(tpllay)
+    info64, infomp = tpl64.info(), tplmp.info()
+
+    out64 = [torch.empty((B, net.n_bus), dtype=torch.float64, device=dev) for _ in range(2)] + \
+        [torch.empty(B, dtype=torch.int32, device=dev) for _ in range(2)] + \
+        [torch.empty(B, dtype=torch.float64, device=dev)]
+    outmp = [x.clone() for x in out64]
+    leaves = {k: d[k].clone().requires_grad_(True) for k in d}
+
+    def layer_step():
+        for v in leaves.values():
+            v.grad = None
+        vm, va = layer(leaves["pd"], leaves["qd"], leaves["pg"], leaves["vset"])
+        L = (torch.relu(vm - 1.05) ** 2).sum() + (torch.relu(0.95 - vm) ** 2).sum() + 0.1 * (va ** 2).sum()
+        L.backward()
+
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    for _ in range(args.warmup):
+        tpl64.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=out64)
+        tplmp.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=outmp)
+        layer_step()
+    torch.cuda.synchronize()
+
+    marks = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e = [ev() for _ in range(4)]
+        e[0].record(stream)
+        tpl64.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=out64)
+        e[1].record(stream)
+        tplmp.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=outmp)
+        e[2].record(stream)
+        layer_step()
+        e[3].record(stream)
+        marks.append(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    t64 = np.array([m[0].elapsed_time(m[1]) for m in marks]) * 1e-3
+    tmp = np.array([m[1].elapsed_time(m[2]) for m in marks]) * 1e-3
+    tfb = np.array([m[2].elapsed_time(m[3]) for m in marks]) * 1e-3
+    it64, st64, fn64 = (x.cpu().numpy() for x in out64[2:])
+    itmp, stmp, fnmp = (x.cpu().numpy() for x in outmp[2:])
+    mp_rate = B / tmp.mean()
+    # dominant kernel: the mixed-precision Newton kernel, one launch per solve
+    bytes_launch = B * algorithmic_bytes_per_solve(net.n_bus, infomp["nnz_lu"], float(itmp.mean()), 4, 2)
+    achieved = bytes_launch / tmp.mean() / 1e9
+
+    res = {
+        "metric": "PF solves/sec (FP32-LU+refine vs FP64) & PF-layer fwd+bwd samples/sec @1e-8pu",
+        "value": mp_rate,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic (seeded meshed grid and lognormal load scenarios)",
+        "config": {"workload": f"{spec.n_bus}-bus synthetic meshed grid, batch {B}, tol {spec.tol:g}",
+                   "n_bus": spec.n_bus, "n_pv": spec.n_pv, "n_branch": spec.n_branch,
+                   "batch": B, "tol": spec.tol, "refine_steps": 2, "parallelism": "single GPU"},
+        "fp64_solves_per_s": B / t64.mean(),
+        "mixed_solves_per_s": mp_rate,
+        "layer_fwd_bwd_samples_per_s": B / tfb.mean(),
+        "ms": {"fp64_solve": 1e3 * t64.mean(), "mixed_solve": 1e3 * tmp.mean(),
+               "layer_fwd_bwd": 1e3 * tfb.mean(), "template_build": 1e3 * t_build},
+        "iterations": {"fp64": np.bincount(it64).tolist(), "mixed": np.bincount(itmp).tolist()},
+        "converged": {"fp64": int((st64 == 0).sum()), "mixed": int((stmp == 0).sum())},
+        "max_final_mismatch": {"fp64": float(fn64.max()), "mixed": float(fnmp.max())},
+        "template": {k: infomp[k] for k in ("n_j", "nnz_j1", "nnzb_lu", "nnz_lu", "fill_ratio",
+                                            "n_levels_l", "n_levels_u", "lds_resident",
+                                            "block_threads", "lds_bytes", "workspace_bytes")},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_newton<float> (mixed-precision Newton, one launch per solve)",
+                     "bytes_per_launch": bytes_launch, "avg_launch_ms": 1e3 * tmp.mean()},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(name, B, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,403 @@
+// C-ABI of the batched Newton power-flow library (declared in sable_pf.h).
+//
+// pf_template_build runs the host symbolic analysis once, uploads the shared
+// pattern, schedules and fill map in one device allocation, and allocates the
+// per-scenario workspace for the whole batch; solve / adjoint calls only
+// enqueue kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pf_kernels.h"
+#include "sable_pf.h"
+#include "symbolic.h"
+
+struct pf_template {
+  sable::Symbolic sym;
+  pf_options opt{};
+  int32_t batch = 0;
+  bool fp32 = false;
+  int nt = 256;
+  bool lds_res = false;
+  size_t lds_bytes = 0;
+  int gmin = 4;
+  int wstride = 0;
+  int device = 0;
+  sable::StateLayout lay{};
+  sable::DevSym ds{};
+  void* d_sym = nullptr;
+  double* ws_d = nullptr;
+  void* ws_t = nullptr;
+  int* ws_i = nullptr;
+  size_t ws_bytes = 0;
+  bool have_factors = false;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return PF_EHIP;
+}
+
+// keeps the caller's current device, switches to the template's for a call
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() { if (prev >= 0) hipSetDevice(prev); }
+};
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+sable::StateLayout make_layout(int n_bus, int nb, int nnzb) {
+  sable::StateLayout L{};
+  const int nbr = round_up(n_bus, 4), v2 = round_up(2 * nb, 4);
+  int o = 0;
+  L.o_e = o; o += nbr; L.o_f = o; o += nbr; L.o_vm = o; o += nbr; L.o_va = o; o += nbr;
+  L.o_ire = o; o += nbr; L.o_iim = o; o += nbr; L.o_ps = o; o += nbr; L.o_qs = o; o += nbr;
+  L.o_dvr = o; o += nbr; L.o_dvi = o; o += nbr; L.o_aux = o; o += nbr;
+  L.o_F = o; o += v2; L.o_dx = o; o += v2; L.o_rr = o; o += v2;
+  L.sd = o;
+  int t = 0;
+  L.o_y = t; t += round_up(2 * nb, 8);
+  L.o_lu = t; t += round_up(4 * nnzb, 8);
+  L.o_dinv = t; t += round_up(4 * nb, 8);
+  L.st = t;
+  return L;
+}
+
+// packs int32 / double host arrays into one device buffer
+struct Packer {
+  std::vector<unsigned char> buf;
+  template <typename V>
+  size_t add(const std::vector<V>& v) {
+    size_t off = (buf.size() + 255) / 256 * 256;
+    buf.resize(off + v.size() * sizeof(V) + 4);
+    if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(V));
+    return off;
+  }
+};
+
+void fill_stats(const sable::Symbolic& S, pf_template_stats* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->n_bus = S.n_bus;
+  o->n_pv = S.n_pv;
+  o->n_pq = S.n_pq;
+  o->n_j = S.nb + S.n_pq;
+  o->nnz_ybus = (int32_t)S.y_ci.size();
+  o->nnz_j1 = S.nnz_j1;
+  o->n_blocks = S.nb;
+  o->nnzb_lu = S.nnzb();
+  o->nnz_lu = S.nnz_lu;
+  o->n_block_updates = S.n_upd;
+  o->n_levels_l = S.n_levels_l();
+  o->n_levels_u = S.n_levels_u();
+  o->max_row_blocks = S.max_row_blocks;
+  o->fill_ratio = S.nnz_j1 > 0 ? (double)S.nnz_lu / (double)S.nnz_j1 : 0.0;
+  o->factor_flops = S.factor_flops;
+}
+
+bool structurally_symmetric(const sable::Symbolic& S) {
+  for (int32_t q : S.y_tr) if (q < 0) return false;
+  return true;
+}
+
+sable::KParams base_params(const pf_template* t) {
+  sable::KParams kp{};
+  kp.s = t->ds;
+  kp.lay = t->lay;
+  kp.ws_d = t->ws_d;
+  kp.ws_t = t->ws_t;
+  kp.ws_i = t->ws_i;
+  kp.max_iter = t->opt.max_iter;
+  kp.refine = t->fp32 ? t->opt.refine_steps : 0;
+  kp.keep = t->opt.keep_factors;
+  kp.gmin = t->gmin;
+  kp.wstride = t->wstride;
+  kp.tol = t->opt.tol;
+  kp.count = t->batch;
+  return kp;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pf_default_options(pf_options* opt) {
+  if (!opt) return;
+  opt->tol = 1e-8;
+  opt->max_iter = 20;
+  opt->precision = PF_FP64;
+  opt->refine_steps = 2;
+  opt->keep_factors = 1;
+  opt->block_threads = 0;
+}
+
+const char* pf_last_error(void) { return g_err.c_str(); }
+
+int pf_ybus_from_branches(int32_t n_bus, int32_t n_branch, const int32_t* from, const int32_t* to,
+                          const double* r, const double* x, const double* b_charging,
+                          int32_t* indptr, int32_t* indices, double* g, double* b,
+                          int32_t capacity, int32_t* nnz_out) {
+  g_err.clear();
+  std::vector<int32_t> rp, ci;
+  std::vector<double> gv, bv;
+  std::string err;
+  int nnz = sable::ybus_from_branches(n_bus, n_branch, from, to, r, x, b_charging, rp, ci, gv, bv, err);
+  if (nnz < 0) return fail(nnz, err);
+  if (nnz_out) *nnz_out = nnz;
+  if (!indptr || !indices || !g || !b) return fail(PF_EINVAL, "pf_ybus_from_branches: null output array");
+  if (nnz > capacity) return fail(PF_EINVAL, "pf_ybus_from_branches: capacity too small");
+  std::copy(rp.begin(), rp.end(), indptr);
+  std::copy(ci.begin(), ci.end(), indices);
+  std::copy(gv.begin(), gv.end(), g);
+  std::copy(bv.begin(), bv.end(), b);
+  return PF_OK;
+}
+
+int pf_symbolic_analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
+                        const int32_t* y_indices, pf_template_stats* out, int32_t* bus_order) {
+  g_err.clear();
+  if (!out) return fail(PF_EINVAL, "pf_symbolic_analyze: out is NULL");
+  if (n_bus < 2 || !y_indptr) return fail(PF_EINVAL, "pf_symbolic_analyze: bad sizes");
+  const int32_t nnz = y_indptr[n_bus];
+  if (nnz < 0) return fail(PF_EINVAL, "pf_symbolic_analyze: bad y_indptr");
+  std::vector<double> ones(nnz, 1.0);
+  sable::Symbolic S;
+  std::string err;
+  int rc = sable::analyze(n_bus, bus_type, y_indptr, y_indices, ones.data(), ones.data(), S, err);
+  if (rc != PF_OK) return fail(rc, err);
+  if (!structurally_symmetric(S)) return fail(PF_EINVAL, "Y_bus pattern must be structurally symmetric");
+  fill_stats(S, out);
+  if (bus_order) std::copy(S.blk_bus.begin(), S.blk_bus.end(), bus_order);
+  return PF_OK;
+}
+
+int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
+                      const int32_t* y_indices, const double* y_g, const double* y_b,
+                      int32_t batch, const pf_options* opt_in, pf_template** out) {
+  g_err.clear();
+  if (!out) return fail(PF_EINVAL, "pf_template_build: out is NULL");
+  *out = nullptr;
+  pf_options opt;
+  pf_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (batch <= 0) return fail(PF_EINVAL, "pf_template_build: batch must be positive");
+  if (!(opt.tol > 0.0) || opt.max_iter < 0 || (opt.precision != PF_FP64 && opt.precision != PF_MIXED) ||
+      opt.refine_steps < 0 || opt.refine_steps > 16 || opt.block_threads < 0 ||
+      opt.block_threads > 1024 || (opt.block_threads % 64) != 0)
+    return fail(PF_EINVAL, "pf_template_build: invalid options");
+
+  pf_template* t = new (std::nothrow) pf_template();
+  if (!t) return fail(PF_ENOMEM, "pf_template_build: host allocation failed");
+  std::string err;
+  int rc = sable::analyze(n_bus, bus_type, y_indptr, y_indices, y_g, y_b, t->sym, err);
+  if (rc != PF_OK) { delete t; return fail(rc, err); }
+  if (!structurally_symmetric(t->sym)) {
+    delete t;
+    return fail(PF_EINVAL, "pf_template_build: Y_bus pattern must be structurally symmetric");
+  }
+  const sable::Symbolic& S = t->sym;
+  t->opt = opt;
+  t->batch = batch;
+  t->fp32 = opt.precision == PF_MIXED;
+  const size_t tsz = t->fp32 ? 4 : 8;
+
+  hipError_t he = hipGetDevice(&t->device);
+  if (he != hipSuccess) { delete t; return hip_fail(he, "pf_template_build: no HIP device"); }
+  hipDeviceProp_t prop;
+  he = hipGetDeviceProperties(&prop, t->device);
+  if (he != hipSuccess) { delete t; return hip_fail(he, "pf_template_build: device query"); }
+  const size_t max_lds = prop.sharedMemPerBlock;
+
+  // ---- launch shape
+  t->lay = make_layout(S.n_bus, S.nb, S.nnzb());
+  const size_t lds_res_bytes = sable::kScratchBytes + 8 * (size_t)t->lay.sd + tsz * (size_t)t->lay.st;
+  const size_t lds_res_limit = std::min<size_t>(max_lds, 80 * 1024);
+  t->lds_res = lds_res_bytes <= lds_res_limit;
+  int nt = opt.block_threads;
+  if (nt == 0) nt = S.nb < 40 ? 64 : (S.nb < 160 ? 128 : 256);
+  t->nt = nt;
+  t->wstride = round_up(4 * S.max_row_blocks, 8);
+  if (t->lds_res) {
+    t->gmin = 4;
+    t->lds_bytes = lds_res_bytes;
+  } else {
+    const size_t budget = std::min<size_t>(max_lds, 64 * 1024) - sable::kScratchBytes;
+    int g = 4;
+    while (g <= 64 && (size_t)(nt / g) * t->wstride * tsz > budget) g <<= 1;
+    if (g > 64) {
+      delete t;
+      return fail(PF_EINVAL, "pf_template_build: a factor row does not fit in LDS for this block size");
+    }
+    t->gmin = g;
+    t->lds_bytes = sable::kScratchBytes + (size_t)(nt / g) * t->wstride * tsz;
+  }
+
+  // ---- device symbolic data
+  std::vector<int32_t> ord_p(S.n_bus, -1), ord_q(S.n_bus, -1);
+  int np = 0, nq = 0;
+  for (int i = 0; i < S.n_bus; ++i) {
+    if (S.bus_type[i] != PF_BUS_SLACK) ord_p[i] = np++;
+    if (S.bus_type[i] == PF_BUS_PQ) ord_q[i] = nq++;
+  }
+  Packer pk;
+  const size_t o_bt = pk.add(S.bus_type), o_bb = pk.add(S.bus_blk), o_blb = pk.add(S.blk_bus);
+  const size_t o_op = pk.add(ord_p), o_oq = pk.add(ord_q);
+  const size_t o_yrp = pk.add(S.y_rp), o_yci = pk.add(S.y_ci), o_ytr = pk.add(S.y_tr);
+  const size_t o_yg = pk.add(S.y_g), o_yb = pk.add(S.y_b);
+  const size_t o_rp = pk.add(S.rp), o_ci = pk.add(S.ci), o_dg = pk.add(S.diag);
+  const size_t o_mi = pk.add(S.mirror), o_src = pk.add(S.lu_src);
+  const size_t o_us = pk.add(S.upd_start), o_ut = pk.add(S.upd_tgt);
+  const size_t o_llp = pk.add(S.lev_l_ptr), o_llr = pk.add(S.lev_l_rows);
+  const size_t o_lup = pk.add(S.lev_u_ptr), o_lur = pk.add(S.lev_u_rows);
+  he = hipMalloc(&t->d_sym, pk.buf.size());
+  if (he != hipSuccess) { delete t; return fail(PF_ENOMEM, "pf_template_build: device allocation (pattern)"); }
+  he = hipMemcpy(t->d_sym, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
+  if (he != hipSuccess) { pf_template_destroy(t); return hip_fail(he, "pf_template_build: upload"); }
+  auto I = [&](size_t o) { return reinterpret_cast<const int*>(static_cast<char*>(t->d_sym) + o); };
+  auto D = [&](size_t o) { return reinterpret_cast<const double*>(static_cast<char*>(t->d_sym) + o); };
+  sable::DevSym& d = t->ds;
+  d.n_bus = S.n_bus; d.nb = S.nb; d.nnzb = S.nnzb(); d.nj = S.nb + S.n_pq; d.npq = S.n_pq;
+  d.npvpq = S.nb; d.nlev_l = S.n_levels_l(); d.nlev_u = S.n_levels_u();
+  d.bus_type = I(o_bt); d.bus_blk = I(o_bb); d.blk_bus = I(o_blb); d.ord_p = I(o_op); d.ord_q = I(o_oq);
+  d.y_rp = I(o_yrp); d.y_ci = I(o_yci); d.y_tr = I(o_ytr); d.y_g = D(o_yg); d.y_b = D(o_yb);
+  d.rp = I(o_rp); d.ci = I(o_ci); d.diag = I(o_dg); d.mirror = I(o_mi); d.lu_src = I(o_src);
+  d.upd_start = I(o_us); d.upd_tgt = I(o_ut);
+  d.lev_l_ptr = I(o_llp); d.lev_l_rows = I(o_llr); d.lev_u_ptr = I(o_lup); d.lev_u_rows = I(o_lur);
+
+  // ---- per-scenario workspace for the whole batch
+  const size_t bd = (size_t)batch * t->lay.sd * 8, bt = (size_t)batch * t->lay.st * tsz,
+               bi = (size_t)batch * 4 * sizeof(int);
+  if (hipMalloc(&t->ws_d, bd) != hipSuccess || hipMalloc(&t->ws_t, bt) != hipSuccess ||
+      hipMalloc(&t->ws_i, bi) != hipSuccess) {
+    pf_template_destroy(t);
+    return fail(PF_ENOMEM, "pf_template_build: device allocation (workspace)");
+  }
+  he = hipMemset(t->ws_i, 0xff, bi);
+  if (he == hipSuccess && t->lds_bytes > 64 * 1024) he = sable::set_lds_limits(t->lds_bytes);
+  if (he == hipSuccess) he = hipDeviceSynchronize();
+  if (he != hipSuccess) { pf_template_destroy(t); return hip_fail(he, "pf_template_build: set-up"); }
+  t->ws_bytes = pk.buf.size() + bd + bt + bi;
+  *out = t;
+  return PF_OK;
+}
+
+int pf_template_info(const pf_template* t, pf_template_stats* out) {
+  g_err.clear();
+  if (!t || !out) return fail(PF_EINVAL, "pf_template_info: NULL argument");
+  fill_stats(t->sym, out);
+  out->workspace_bytes = t->ws_bytes;
+  out->batch = t->batch;
+  out->lds_resident = t->lds_res ? 1 : 0;
+  out->block_threads = t->nt;
+  out->lds_bytes = (int32_t)t->lds_bytes;
+  return PF_OK;
+}
+
+int pf_template_destroy(pf_template* t) {
+  g_err.clear();
+  if (!t) return PF_OK;
+  DeviceGuard g(t->device);
+  hipDeviceSynchronize();
+  if (t->d_sym) hipFree(t->d_sym);
+  if (t->ws_d) hipFree(t->ws_d);
+  if (t->ws_t) hipFree(t->ws_t);
+  if (t->ws_i) hipFree(t->ws_i);
+  delete t;
+  return PF_OK;
+}
+
+int pf_solve_batch(pf_template* t, const double* pd, const double* qd, const double* pg,
+                   const double* vset, double* vm, double* va, int32_t* iters, int32_t* status,
+                   double* final_mismatch, void* hip_stream) {
+  g_err.clear();
+  if (!t) return fail(PF_EINVAL, "pf_solve_batch: template is NULL");
+  if (!pd || !qd || !vset || !vm || !va) return fail(PF_EINVAL, "pf_solve_batch: NULL input/output array");
+  DeviceGuard g(t->device);
+  sable::KParams kp = base_params(t);
+  kp.mode = sable::MODE_SOLVE;
+  kp.pd = pd; kp.qd = qd; kp.pg = pg; kp.vset = vset;
+  kp.vm_out = vm; kp.va_out = va;
+  kp.iters_out = iters; kp.status_out = status; kp.fnorm_out = final_mismatch;
+  hipError_t he = sable::launch_newton(kp, t->fp32, t->batch, t->nt, t->lds_bytes, t->lds_res,
+                                       static_cast<hipStream_t>(hip_stream));
+  if (he != hipSuccess) return hip_fail(he, "pf_solve_batch: launch");
+  t->have_factors = t->opt.keep_factors != 0;
+  return PF_OK;
+}
+
+int pf_adjoint_batch(pf_template* t, const double* g_vm, const double* g_va, double* g_pd,
+                     double* g_qd, double* g_pg, double* g_vset, void* hip_stream) {
+  g_err.clear();
+  if (!t) return fail(PF_EINVAL, "pf_adjoint_batch: template is NULL");
+  if (!g_vm || !g_va) return fail(PF_EINVAL, "pf_adjoint_batch: NULL gradient input");
+  if (!t->have_factors)
+    return fail(PF_ESTATE, "pf_adjoint_batch: needs a preceding pf_solve_batch with keep_factors=1");
+  DeviceGuard g(t->device);
+  sable::KParams kp = base_params(t);
+  kp.mode = sable::MODE_SOLVE;
+  kp.g_vm = g_vm; kp.g_va = g_va;
+  kp.g_pd = g_pd; kp.g_qd = g_qd; kp.g_pg = g_pg; kp.g_vset = g_vset;
+  hipError_t he = sable::launch_adjoint(kp, t->fp32, t->batch, t->nt, static_cast<hipStream_t>(hip_stream));
+  if (he != hipSuccess) return hip_fail(he, "pf_adjoint_batch: launch");
+  return PF_OK;
+}
+
+int pf_eval_batch(pf_template* t, int32_t mode, int32_t count, const double* pd, const double* qd,
+                  const double* pg, const double* vset, const double* vm, const double* va,
+                  const double* rhs, double* out, void* hip_stream) {
+  g_err.clear();
+  if (!t) return fail(PF_EINVAL, "pf_eval_batch: template is NULL");
+  if (count <= 0 || count > t->batch) return fail(PF_EINVAL, "pf_eval_batch: count out of range");
+  if (!pd || !qd || !vset || !vm || !va || !out) return fail(PF_EINVAL, "pf_eval_batch: NULL array");
+  if (mode == PF_EVAL_ADJOINT && !rhs) return fail(PF_EINVAL, "pf_eval_batch: rhs is NULL");
+  DeviceGuard g(t->device);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  sable::KParams kp = base_params(t);
+  kp.pd = pd; kp.qd = qd; kp.pg = pg; kp.vset = vset; kp.vm_in = vm; kp.va_in = va;
+  kp.rhs = rhs; kp.out = out; kp.count = count;
+  t->have_factors = false;   // the evaluation reuses the workspace
+  hipError_t he;
+  switch (mode) {
+    case PF_EVAL_MISMATCH:
+      kp.mode = sable::MODE_EVAL_MISMATCH;
+      he = sable::launch_newton(kp, t->fp32, count, t->nt, t->lds_bytes, t->lds_res, st);
+      break;
+    case PF_EVAL_STEP:
+      kp.mode = sable::MODE_EVAL_STEP;
+      he = sable::launch_newton(kp, t->fp32, count, t->nt, t->lds_bytes, t->lds_res, st);
+      break;
+    case PF_EVAL_JACOBIAN:
+      he = sable::launch_jacobian_dense(kp, count, st);
+      break;
+    case PF_EVAL_ADJOINT:
+      kp.mode = sable::MODE_EVAL_FACTOR;
+      he = sable::launch_newton(kp, t->fp32, count, t->nt, t->lds_bytes, t->lds_res, st);
+      if (he == hipSuccess) {
+        kp.mode = sable::MODE_EVAL_ADJOINT;
+        he = sable::launch_adjoint(kp, t->fp32, count, t->nt, st);
+      }
+      break;
+    default:
+      return fail(PF_EINVAL, "pf_eval_batch: unknown mode");
+  }
+  if (he != hipSuccess) return hip_fail(he, "pf_eval_batch: launch");
+  return PF_OK;
+}
+
+}  // extern "C"

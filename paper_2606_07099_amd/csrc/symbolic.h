@@ -1,0 +1,80 @@
+// One-time symbolic analysis for the batched Newton power flow (host C++).
+//
+// The step-1 Jacobian J1 of every scenario shares one sparsity pattern, set
+// by the Y_bus pattern and the bus-type partition (symbolic-analysis and
+// BDE-layout passages of Sec. III-B).  This module builds, once per network:
+//
+//  * a fill-reducing elimination order of the non-slack buses (exact minimum
+//    degree on the bus graph, ties to the lowest bus index);
+//  * the 2x2-block pattern of L+U: every non-slack bus i owns the block
+//    unknowns (theta_i, |V|_i) and the block equations (dP_i, dQ_i); on a PV
+//    bus the |V| unknown and the dQ row are padding (identity diagonal, zero
+//    coupling), so the block system has exactly the Newton solution;
+//  * row-oriented ("up-looking") elimination lists: for each L block (a,k)
+//    the row-relative targets in row a of the U blocks of row k;
+//  * level sets for the factorisation / forward solve (dependencies on
+//    earlier rows) and for the backward solve (dependencies on later rows);
+//  * the position of the transposed block of every block (for the adjoint's
+//    transposed solves), and the Y_bus entry that feeds every block (the
+//    Jacobian fill map of the value-update kernel, Algorithm 1).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace sable {
+
+struct Symbolic {
+  int32_t n_bus = 0;
+  int32_t slack = -1;
+  int32_t nb = 0;                    // block rows = non-slack buses
+  std::vector<int32_t> bus_type;     // [n_bus] 0 PQ, 1 PV, 2 slack
+  std::vector<int32_t> blk_bus;      // [nb] bus of block row a (elimination order)
+  std::vector<int32_t> bus_blk;      // [n_bus] block row of a bus, -1 for the slack
+
+  // Y_bus (CSR, columns sorted)
+  std::vector<int32_t> y_rp, y_ci;
+  std::vector<double> y_g, y_b;
+  std::vector<int32_t> y_tr;         // [nnzY] position of the transposed entry
+
+  // block L+U pattern, CSR over block rows in elimination order, sorted columns
+  std::vector<int32_t> rp, ci, diag; // rp [nb+1], ci [nnzb], diag [nb]
+  std::vector<int32_t> prow;         // [nnzb] block row of each position
+  std::vector<int32_t> mirror;       // [nnzb] position of the transposed block
+  std::vector<int32_t> lu_src;       // [nnzb] Y_bus entry of the block, -1 if fill-in
+
+  // elimination lists: for L position p = (a,k): targets for U(k, >k)
+  std::vector<int32_t> upd_start;    // [nnzb] (only L positions meaningful)
+  std::vector<int32_t> upd_tgt;      // row-relative block offsets inside row a
+
+  // level schedules
+  std::vector<int32_t> lev_l_ptr, lev_l_rows;   // factor / forward solve / U^T solve
+  std::vector<int32_t> lev_u_ptr, lev_u_rows;   // backward solve / L^T solve
+
+  // statistics
+  int64_t nnz_j1 = 0;        // scalar nonzeros of J1 (real unknowns only)
+  int64_t nnz_lu = 0;        // scalar nonzeros of L+U over real unknowns
+  int64_t n_upd = 0;         // block multiply-subtract operations per factorisation
+  double factor_flops = 0;   // scalar flops of one factorisation on 2x2 blocks
+  int32_t max_row_blocks = 0;
+  int32_t n_pv = 0, n_pq = 0;
+
+  int32_t nnzb() const { return (int32_t)ci.size(); }
+  int32_t n_levels_l() const { return (int32_t)lev_l_ptr.size() - 1; }
+  int32_t n_levels_u() const { return (int32_t)lev_u_ptr.size() - 1; }
+};
+
+// Returns 0 on success; on failure a negative PF_E* code and a message.
+int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
+            const int32_t* y_indices, const double* y_g, const double* y_b,
+            Symbolic& out, std::string& err);
+
+// pi-model branch admittances assembled into CSR (columns sorted, duplicate
+// branches summed).  Returns nnz, or a negative error code.
+int ybus_from_branches(int32_t n_bus, int32_t n_branch, const int32_t* f, const int32_t* t,
+                       const double* r, const double* x, const double* bc,
+                       std::vector<int32_t>& rp, std::vector<int32_t>& ci,
+                       std::vector<double>& g, std::vector<double>& b, std::string& err);
+
+}  // namespace sable

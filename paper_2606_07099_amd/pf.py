@@ -1,0 +1,191 @@
+"""Python handle on a power-flow template (ctypes marshalling only).
+
+Torch is used for device memory and streams: batch arrays are contiguous
+float64 CUDA tensors of shape [batch, n_bus]; calls are enqueued on the
+current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (PFError, PFOptions, PFStats, check, lib, PF_FP64, PF_MIXED, PF_EVAL_ADJOINT,
+                   PF_EVAL_JACOBIAN, PF_EVAL_MISMATCH, PF_EVAL_STEP)
+
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_F64P = ctypes.POINTER(ctypes.c_double)
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_I32P)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_F64P)
+
+
+def ybus_from_branches(n_bus, f, t, r, x, bc):
+    """Y_bus CSR (indptr, indices, g, b) of a pi-model branch list, by the library."""
+    L = lib()
+    f_, fp = _i32(f)
+    t_, tp = _i32(t)
+    r_, rp = _f64(r)
+    x_, xp = _f64(x)
+    b_, bp = _f64(bc)
+    m = int(f_.shape[0])
+    cap = 4 * m + n_bus
+    indptr = np.zeros(n_bus + 1, np.int32)
+    ind = np.zeros(cap, np.int32)
+    g = np.zeros(cap)
+    b = np.zeros(cap)
+    nnz = ctypes.c_int32(0)
+    check(L.pf_ybus_from_branches(n_bus, m, fp, tp, rp, xp, bp, indptr.ctypes.data_as(_I32P),
+                                  ind.ctypes.data_as(_I32P), g.ctypes.data_as(_F64P),
+                                  b.ctypes.data_as(_F64P), cap, ctypes.byref(nnz)))
+    k = nnz.value
+    return indptr, ind[:k].copy(), g[:k].copy(), b[:k].copy()
+
+
+def symbolic_analyze(n_bus, bus_type, indptr, indices):
+    """Host-only symbolic statistics and bus elimination order (no GPU needed)."""
+    L = lib()
+    st = PFStats()
+    bt, btp = _i32(bus_type)
+    ip, ipp = _i32(indptr)
+    ix, ixp = _i32(indices)
+    order = np.zeros(n_bus - 1, np.int32)
+    check(L.pf_symbolic_analyze(n_bus, btp, ipp, ixp, ctypes.byref(st), order.ctypes.data_as(_I32P)))
+    return st.as_dict(), order
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class PFTemplate:
+    """A network + batch size: the one-time symbolic analysis and the device
+    workspace of ``pf_template_build``."""
+
+    def __init__(self, n_bus, bus_type, indptr, indices, g, b, batch, *, tol=1e-8, max_iter=20,
+                 precision="fp64", refine_steps=2, keep_factors=True, block_threads=0):
+        L = lib()
+        opt = PFOptions()
+        L.pf_default_options(ctypes.byref(opt))
+        opt.tol = float(tol)
+        opt.max_iter = int(max_iter)
+        opt.precision = {"fp64": PF_FP64, "mixed": PF_MIXED}[precision]
+        opt.refine_steps = int(refine_steps)
+        opt.keep_factors = 1 if keep_factors else 0
+        opt.block_threads = int(block_threads)
+        self.n_bus = int(n_bus)
+        self.batch = int(batch)
+        self.precision = precision
+        self._bt, btp = _i32(bus_type)
+        self._ip, ipp = _i32(indptr)
+        self._ix, ixp = _i32(indices)
+        self._g, gp = _f64(g)
+        self._b, bp = _f64(b)
+        h = ctypes.c_void_p()
+        check(L.pf_template_build(self.n_bus, btp, ipp, ixp, gp, bp, self.batch, ctypes.byref(opt),
+                                  ctypes.byref(h)))
+        self._h = h
+        self._solve_id = 0
+
+    @classmethod
+    def from_network(cls, net, batch, **kw):
+        indptr, ind, g, b = ybus_from_branches(net.n_bus, net.f, net.t, net.r, net.x, net.bc)
+        return cls(net.n_bus, net.bus_type, indptr, ind, g, b, batch, **kw)
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pf_template_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        st = PFStats()
+        check(lib().pf_template_info(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    @property
+    def n_j(self) -> int:
+        return self.info()["n_j"]
+
+    # ------------------------------------------------------------------
+    def _check(self, name, x, rows=None):
+        import torch
+        rows = self.batch if rows is None else rows
+        if not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_cuda:
+            raise TypeError(f"{name} must be a float64 CUDA tensor")
+        if not x.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if x.dim() != 2 or x.shape[0] < rows or x.shape[1] != self.n_bus:
+            raise ValueError(f"{name} must have shape [{rows}, {self.n_bus}], got {tuple(x.shape)}")
+        return ctypes.c_void_p(x.data_ptr())
+
+    def solve(self, pd, qd, pg, vset, *, out=None, stream=None):
+        """Newton solve of the whole batch from the flat start.  Returns
+        (vm, va, iters, status, final_mismatch) as device tensors."""
+        import torch
+        dev = pd.device
+        if out is None:
+            vm = torch.empty((self.batch, self.n_bus), dtype=torch.float64, device=dev)
+            va = torch.empty_like(vm)
+            iters = torch.empty(self.batch, dtype=torch.int32, device=dev)
+            status = torch.empty_like(iters)
+            fn = torch.empty(self.batch, dtype=torch.float64, device=dev)
+        else:
+            vm, va, iters, status, fn = out
+        args = [self._check("pd", pd), self._check("qd", qd),
+                self._check("pg", pg) if pg is not None else ctypes.c_void_p(0),
+                self._check("vset", vset), self._check("vm", vm), self._check("va", va)]
+        check(lib().pf_solve_batch(self._h, *args, ctypes.c_void_p(iters.data_ptr()),
+                                   ctypes.c_void_p(status.data_ptr()), ctypes.c_void_p(fn.data_ptr()),
+                                   _stream_ptr(stream)))
+        self._solve_id += 1
+        return vm, va, iters, status, fn
+
+    def adjoint(self, g_vm, g_va, *, stream=None):
+        """Gradients (g_pd, g_qd, g_pg, g_vset) of the most recent solve."""
+        import torch
+        outs = [torch.empty_like(g_vm) for _ in range(4)]
+        check(lib().pf_adjoint_batch(self._h, self._check("g_vm", g_vm), self._check("g_va", g_va),
+                                     *[ctypes.c_void_p(o.data_ptr()) for o in outs],
+                                     _stream_ptr(stream)))
+        return tuple(outs)
+
+    def evaluate(self, mode, pd, qd, pg, vset, vm, va, rhs=None, count=None, *, stream=None):
+        """Kernel-level evaluation at a given state (see ``pf_eval_batch``)."""
+        import torch
+        count = self.batch if count is None else int(count)
+        nj = self.n_j
+        shape = (count, nj, nj) if mode == PF_EVAL_JACOBIAN else (count, nj)
+        out = torch.empty(shape, dtype=torch.float64, device=vm.device)
+        r = ctypes.c_void_p(0)
+        if rhs is not None:
+            if rhs.dtype != torch.float64 or not rhs.is_contiguous() or tuple(rhs.shape[1:]) != (nj,):
+                raise ValueError("rhs must be contiguous float64 [count, n_j]")
+            r = ctypes.c_void_p(rhs.data_ptr())
+        check(lib().pf_eval_batch(self._h, int(mode), count,
+                                  self._check("pd", pd, count), self._check("qd", qd, count),
+                                  self._check("pg", pg, count) if pg is not None else ctypes.c_void_p(0),
+                                  self._check("vset", vset, count), self._check("vm", vm, count),
+                                  self._check("va", va, count), r, ctypes.c_void_p(out.data_ptr()),
+                                  _stream_ptr(stream)))
+        return out
+
+
+__all__ = ["PFTemplate", "ybus_from_branches", "symbolic_analyze", "PFError", "PF_EVAL_MISMATCH",
+           "PF_EVAL_JACOBIAN", "PF_EVAL_STEP", "PF_EVAL_ADJOINT"]

@@ -1,0 +1,84 @@
+"""GPU adjoint (implicit-differentiation gradients) against the dense FP64
+oracle gradient and against central finite differences, through the C ABI
+and through the autograd layer."""
+import numpy as np
+import pytest
+
+from gpu_helpers import make_gpu_case, to_dev
+from oracle.adjoint import adjoint, fd_gradient, loss, loss_grad
+from oracle.newton import Index, newton
+from oracle.ybus import ybus_of
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+
+
+def _gpu_grads(tpl, d, device):
+    import torch
+    vm, va, iters, status, fn = tpl.solve(d["pd"], d["qd"], d["pg"], d["vset"])
+    g_vm, g_va = loss_grad(vm.cpu().numpy(), va.cpu().numpy())
+    out = tpl.adjoint(to_dev(g_vm, device), to_dev(g_va, device))
+    torch.cuda.synchronize()
+    return (vm.cpu().numpy(), va.cpu().numpy(), status.cpu().numpy(),
+            [o.cpu().numpy() for o in out])
+
+
+@pytest.mark.parametrize("name,precision,n_check", [("c0", "fp64", 64), ("c3", "fp64", 8),
+                                                    ("c1", "mixed", 16), ("c3", "mixed", 8)])
+def test_adjoint_matches_dense_oracle_gradient(name, precision, n_check, device):
+    spec, net, sc, tpl, d, tol = make_gpu_case(name, device, precision=precision)
+    vm, va, status, (g_pd, g_qd, g_pg, g_vs) = _gpu_grads(tpl, d, device)
+    assert np.all(status == 0)
+    Y = ybus_of(net)
+    for b in np.unique(np.linspace(0, sc.batch - 1, n_check).astype(int)):
+        r = newton(Y, net.bus_type, sc.pd[b], sc.qd[b], sc.pg[b], sc.vset[b], tol=tol)
+        gv, ga = loss_grad(r.vm, r.va)
+        g = adjoint(Y, net.bus_type, r.vm, r.va, gv, ga)
+        ours = np.concatenate([g_pd[b], g_qd[b], g_pg[b], g_vs[b]])
+        ref = np.concatenate([g.pd, g.qd, g.pg, g.vset])
+        assert _rel(ours, ref) <= 1e-6, (b, _rel(ours, ref))
+        # structural zeros: no load gradient at the slack, q only on PQ, p_g only on PV
+        assert g_pd[b][net.bus_type == 2].tolist() == [0.0]
+        assert np.all(g_qd[b][net.bus_type != 0] == 0.0)
+        assert np.all(g_pg[b][net.bus_type != 1] == 0.0)
+        assert np.all(g_vs[b][net.bus_type == 0] == 0.0)
+
+
+def test_adjoint_matches_central_differences(device):
+    spec, net, sc, tpl, d, tol = make_gpu_case("c0", device, batch=4, tol=1e-12)
+    vm, va, status, (g_pd, g_qd, g_pg, g_vs) = _gpu_grads(tpl, d, device)
+    Y = ybus_of(net)
+    idx = Index.of(net.bus_type)
+    for b in range(2):
+        for which, coords, ours in (("pd", idx.pvpq, g_pd[b]), ("qd", idx.pq, g_qd[b]),
+                                    ("pg", idx.pv, g_pg[b]),
+                                    ("vset", np.concatenate([idx.pv, idx.ref]), g_vs[b])):
+            fd = fd_gradient(Y, net.bus_type, sc.pd[b], sc.qd[b], sc.pg[b], sc.vset[b], which, coords)
+            assert _rel(ours[coords], fd) <= 1e-6, (which, _rel(ours[coords], fd))
+
+
+def test_pf_layer_autograd_end_to_end(device):
+    import torch
+    from paper_2606_07099_amd import PFLayer
+    spec, net, sc, tpl, d, tol = make_gpu_case("c3", device, batch=64, tol=1e-10)
+    layer = PFLayer(tpl)
+    leaves = {k: d[k].clone().requires_grad_(True) for k in ("pd", "qd", "pg", "vset")}
+    vm, va = layer(leaves["pd"], leaves["qd"], leaves["pg"], leaves["vset"])
+    L = (torch.relu(vm - 1.05) ** 2).sum() + (torch.relu(0.95 - vm) ** 2).sum() + 0.1 * (va ** 2).sum()
+    L.backward()
+    Y = ybus_of(net)
+    lsum = 0.0
+    for b in (0, 31, 63):
+        r = newton(Y, net.bus_type, sc.pd[b], sc.qd[b], sc.pg[b], sc.vset[b], tol=1e-10)
+        gv, ga = loss_grad(r.vm, r.va)
+        g = adjoint(Y, net.bus_type, r.vm, r.va, gv, ga)
+        for k in ("pd", "qd", "pg", "vset"):
+            ours = leaves[k].grad[b].cpu().numpy()
+            assert _rel(ours, getattr(g, k)) <= 1e-6, (k, b)
+    for b in range(64):
+        r = newton(Y, net.bus_type, sc.pd[b], sc.qd[b], sc.pg[b], sc.vset[b], tol=1e-10)
+        lsum += loss(r.vm, r.va)
+    assert abs(L.item() - lsum) <= 1e-9 * max(1.0, abs(lsum))
