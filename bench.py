@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--workload", default="c1", help="grid name in gen.grids.SPECS")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-reference-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first, as the known-size "
+                         "reference for HBM byte counters")
     return ap.parse_args()
 
 
@@ -126,6 +129,12 @@ def main():
         L = (torch.relu(vm - 1.05) ** 2).sum() + (torch.relu(0.95 - vm) ** 2).sum() + 0.1 * (va ** 2).sum()
         L.backward()
 
+    if args.copy_reference_mib:
+        src = torch.ones(args.copy_reference_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     stream = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     for _ in range(args.warmup):
@@ -186,7 +195,7 @@ def main():
         "max_final_mismatch": {"fp64": float(fn64.max()), "mixed": float(fnmp.max())},
         "template": {k: infomp[k] for k in ("n_j", "nnz_j1", "nnzb_lu", "nnz_lu", "fill_ratio",
                                             "n_levels_l", "n_levels_u", "lds_resident",
-                                            "block_threads", "lds_bytes", "workspace_bytes")},
+                                            "block_threads", "lds_bytes", "slice_width", "workspace_bytes")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_newton<float> (mixed-precision Newton, one launch per solve)",

@@ -24,7 +24,11 @@ experimental-setup section, kept here as ``scenario_mode="uniform10"``):
   for P and Q), and every PV bus dispatches 0.95 * sum_b(p_d) / n_PV;
 * ``load_factor`` < 1 scales the nominal loads (and hence the dispatch)
   down; it is the feasibility back-off described in the design doc and its
-  per-grid value was chosen by ``oracle/calibrate_load_factor.py``.
+  per-grid value was chosen by ``oracle/calibrate_load_factor.py``;
+* ``z_scale`` multiplies the drawn r, x and b: per-unit line parameters grow
+  with line length, and on the 9241-bus grid (same unit square) the lines
+  are sqrt(9241/118) times shorter than on the 118-bus grid.  Without it no
+  load level converges from the flat start on that grid.
 
 Random streams: ``numpy.random.default_rng(SeedSequence([seed, grid_id]))``
 for the network, ``SeedSequence([seed, grid_id, 1])`` for the scenarios, with
@@ -51,6 +55,7 @@ class GridSpec:
     sigma: float           # LogNormal sigma of the per-(scenario, bus) load scale
     tol: float             # Newton tolerance on ||F1||_inf in pu
     load_factor: float = 1.0
+    z_scale: float = 1.0   # multiplies the drawn r, x and b (per-unit parameters ~ line length)
     knn: int = 6
 
 
@@ -61,7 +66,8 @@ SPECS = {
     "c1": GridSpec("c1", 1, 118, 53, 177, 1024, 0.10, 1e-8, load_factor=0.9 ** 7),
     "c2": GridSpec("c2", 2, 1354, 260, 1896, 4096, 0.15, 1e-8, load_factor=0.9 ** 26),
     "c3": GridSpec("c3", 3, 300, 69, 420, 2048, 0.10, 1e-10, load_factor=0.9 ** 17),
-    "c4": GridSpec("c4", 4, 9241, 1400, 12013, 256, 0.10, 1e-8, load_factor=1.0),
+    "c4": GridSpec("c4", 4, 9241, 1400, 12013, 256, 0.10, 1e-8, load_factor=1.0,
+                   z_scale=(118 / 9241) ** 0.5),
 }
 
 
@@ -200,9 +206,9 @@ def make_network(spec: GridSpec, seed: int = 0) -> Network:
     pv = np.sort(rng.choice(np.arange(1, n), size=spec.n_pv, replace=False))
     bus_type[pv] = PV
 
-    r = rng.uniform(0.005, 0.05, m)
+    r = rng.uniform(0.005, 0.05, m) * spec.z_scale
     x = r * rng.uniform(3.0, 10.0, m)
-    bc = rng.uniform(0.0, 0.05, m)
+    bc = rng.uniform(0.0, 0.05, m) * spec.z_scale
 
     vset = np.ones(n)
     vset[pv] = rng.uniform(0.98, 1.05, pv.size)

@@ -70,7 +70,9 @@ extern "C" {
 #define PF_STATUS_CONVERGED 0   /* ||F1||_inf < tol */
 #define PF_STATUS_MAX_ITER 1    /* still >= tol after max_iter updates */
 #define PF_STATUS_NON_FINITE 2  /* mismatch became NaN or Inf */
-#define PF_STATUS_ZERO_PIVOT 3  /* |pivot| <= 1e-14 * max|row| in the LU */
+#define PF_STATUS_ZERO_PIVOT 3  /* a 2x2 pivot block is numerically singular: one of its two
+                                   scalar pivots is <= eps * |row of the block| (eps = 1e-14
+                                   for FP64 factors, 1e-7 for FP32) or its inverse is not finite */
 
 typedef struct pf_template pf_template; /* opaque */
 
@@ -104,6 +106,7 @@ typedef struct {
   int32_t lds_resident;    /* 1: factors and state of a scenario live in LDS */
   int32_t block_threads;   /* threads per workgroup used by the solve kernels */
   int32_t lds_bytes;       /* dynamic LDS per workgroup */
+  int32_t slice_width;     /* scenarios per workgroup of the Newton kernel */
 } pf_template_stats;
 
 /* Fills *opt with the defaults listed above.  Never fails. */

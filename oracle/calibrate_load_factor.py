@@ -44,6 +44,8 @@ def calibrate(name: str, verbose=True) -> float:
     if nominal_ok(name, 1.0, verbose):
         return 1.0
     lo, hi = 0, 64
+    if not nominal_ok(name, 0.9 ** hi, verbose):
+        raise RuntimeError(f"{name}: no load factor down to 0.9**{hi} converges")
     while hi - lo > 1:
         mid = (lo + hi) // 2
         if nominal_ok(name, 0.9 ** mid, verbose):

@@ -37,7 +37,7 @@ class PFStats(ctypes.Structure):
                 ("fill_ratio", ctypes.c_double), ("factor_flops", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t), ("batch", ctypes.c_int32),
                 ("lds_resident", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("slice_width", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -26,9 +26,12 @@ struct pf_template {
   size_t lds_bytes = 0;
   int gmin = 4;
   int wstride = 0;
+  int slice = 1;             // scenarios per workgroup
   int device = 0;
-  sable::StateLayout lay{};
-  sable::DevSym ds{};
+  sable::StateLayout lay{};  // HBM workspace, per scenario
+  sable::StateLayout llay{}; // inside an LDS-resident slice, per scenario
+  sable::SymOffsets so{};
+  sable::Dims dims{};
   void* d_sym = nullptr;
   double* ws_d = nullptr;
   void* ws_t = nullptr;
@@ -55,10 +58,10 @@ int hip_fail(hipError_t e, const char* what) {
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
     else prev = -1;
   }
-  ~DeviceGuard() { if (prev >= 0) hipSetDevice(prev); }
+  ~DeviceGuard() { if (prev >= 0) (void)hipSetDevice(prev); }
 };
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
@@ -80,13 +83,40 @@ sable::StateLayout make_layout(int n_bus, int nb, int nnzb) {
   return L;
 }
 
+// compact per-scenario layout inside an LDS-resident slice: the refinement
+// vectors only exist in the mixed-precision mode, the adjoint scratch never
+sable::StateLayout make_lds_layout(int n_bus, int nb, int nnzb, bool mixed) {
+  sable::StateLayout L{};
+  int o = 0;
+  L.o_e = o; o += n_bus; L.o_f = o; o += n_bus; L.o_vm = o; o += n_bus; L.o_va = o; o += n_bus;
+  L.o_ire = o; o += n_bus; L.o_iim = o; o += n_bus; L.o_ps = o; o += n_bus; L.o_qs = o; o += n_bus;
+  L.o_F = o; o += 2 * nb; L.o_dx = o; o += 2 * nb;
+  if (mixed) {
+    L.o_dvr = o; o += n_bus; L.o_dvi = o; o += n_bus; L.o_rr = o; o += 2 * nb;
+  } else {
+    L.o_dvr = L.o_dvi = L.o_rr = 0;
+  }
+  L.o_aux = 0;
+  L.sd = round_up(o, 2);
+  int t = 0;
+  L.o_y = t; t += 2 * nb;
+  L.o_lu = t; t += 4 * nnzb;
+  L.o_dinv = t; t += 4 * nb;
+  L.st = round_up(t, 4);
+  return L;
+}
+
 // packs int32 / double host arrays into one device buffer
 struct Packer {
   std::vector<unsigned char> buf;
+  size_t align() {
+    buf.resize((buf.size() + 15) / 16 * 16);
+    return buf.size();
+  }
   template <typename V>
   size_t add(const std::vector<V>& v) {
-    size_t off = (buf.size() + 255) / 256 * 256;
-    buf.resize(off + v.size() * sizeof(V) + 4);
+    size_t off = (buf.size() + 15) / 16 * 16;
+    buf.resize(off + v.size() * sizeof(V));
     if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(V));
     return off;
   }
@@ -118,8 +148,11 @@ bool structurally_symmetric(const sable::Symbolic& S) {
 
 sable::KParams base_params(const pf_template* t) {
   sable::KParams kp{};
-  kp.s = t->ds;
+  kp.dims = t->dims;
+  kp.so = t->so;
+  kp.sym = static_cast<const unsigned char*>(t->d_sym);
   kp.lay = t->lay;
+  kp.llay = t->llay;
   kp.ws_d = t->ws_d;
   kp.ws_t = t->ws_t;
   kp.ws_i = t->ws_i;
@@ -224,19 +257,59 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   if (he != hipSuccess) { delete t; return hip_fail(he, "pf_template_build: device query"); }
   const size_t max_lds = prop.sharedMemPerBlock;
 
-  // ---- launch shape
+  // ---- device symbolic image: the arrays the Newton kernel reads first
+  // (copied whole into LDS by LDS-resident slices), then the rest
+  std::vector<int32_t> ord_p(S.n_bus, -1), ord_q(S.n_bus, -1);
+  int np = 0, nq = 0;
+  for (int i = 0; i < S.n_bus; ++i) {
+    if (S.bus_type[i] != PF_BUS_SLACK) ord_p[i] = np++;
+    if (S.bus_type[i] == PF_BUS_PQ) ord_q[i] = nq++;
+  }
+  Packer pk;
+  sable::SymOffsets& so = t->so;
+  so.bus_type = (int)pk.add(S.bus_type); so.bus_blk = (int)pk.add(S.bus_blk);
+  so.blk_bus = (int)pk.add(S.blk_bus); so.y_rp = (int)pk.add(S.y_rp); so.y_ci = (int)pk.add(S.y_ci);
+  so.y_g = (int)pk.add(S.y_g); so.y_b = (int)pk.add(S.y_b);
+  so.rp = (int)pk.add(S.rp); so.ci = (int)pk.add(S.ci); so.diag = (int)pk.add(S.diag);
+  so.lu_src = (int)pk.add(S.lu_src); so.upd_start = (int)pk.add(S.upd_start);
+  so.upd_tgt = (int)pk.add(S.upd_tgt);
+  so.lev_l_ptr = (int)pk.add(S.lev_l_ptr); so.lev_l_rows = (int)pk.add(S.lev_l_rows);
+  so.lev_u_ptr = (int)pk.add(S.lev_u_ptr); so.lev_u_rows = (int)pk.add(S.lev_u_rows);
+  so.newton_bytes = (int)pk.align();
+  so.mirror = (int)pk.add(S.mirror); so.y_tr = (int)pk.add(S.y_tr);
+  so.ord_p = (int)pk.add(ord_p); so.ord_q = (int)pk.add(ord_q);
+  so.total_bytes = (int)pk.align();
+  sable::Dims& dm = t->dims;
+  dm.n_bus = S.n_bus; dm.nb = S.nb; dm.nnzb = S.nnzb(); dm.nj = S.nb + S.n_pq; dm.npq = S.n_pq;
+  dm.npvpq = S.nb; dm.nlev_l = S.n_levels_l(); dm.nlev_u = S.n_levels_u();
+
+  // ---- launch shape: LDS-resident slices of S scenarios when they fit,
+  // choosing S to maximise the scenarios resident per CU; HBM-resident
+  // single-scenario workgroups otherwise
   t->lay = make_layout(S.n_bus, S.nb, S.nnzb());
-  const size_t lds_res_bytes = sable::kScratchBytes + 8 * (size_t)t->lay.sd + tsz * (size_t)t->lay.st;
-  const size_t lds_res_limit = std::min<size_t>(max_lds, 80 * 1024);
-  t->lds_res = lds_res_bytes <= lds_res_limit;
+  t->llay = make_lds_layout(S.n_bus, S.nb, S.nnzb(), t->fp32);
+  const size_t lds_cu = std::max<size_t>(max_lds, (size_t)prop.maxSharedMemoryPerMultiProcessor);
+  const size_t per_scen = 8 * (size_t)t->llay.sd + tsz * (size_t)t->llay.st;
+  int best_s = 0;
+  size_t best_score = 0;
+  for (int sl : {8, 4, 2, 1}) {
+    const size_t need = sable::kScratchBytes + (size_t)so.newton_bytes + sl * per_scen;
+    if (need > max_lds) continue;
+    const size_t score = (lds_cu / need) * sl;
+    if (score > best_score) { best_score = score; best_s = sl; }
+  }
   int nt = opt.block_threads;
-  if (nt == 0) nt = S.nb < 40 ? 64 : (S.nb < 160 ? 128 : 256);
-  t->nt = nt;
   t->wstride = round_up(4 * S.max_row_blocks, 8);
-  if (t->lds_res) {
+  if (best_s > 0) {
+    t->lds_res = true;
+    t->slice = best_s;
     t->gmin = 4;
-    t->lds_bytes = lds_res_bytes;
+    t->lds_bytes = sable::kScratchBytes + (size_t)so.newton_bytes + best_s * per_scen;
+    if (nt == 0) nt = 256;
   } else {
+    t->lds_res = false;
+    t->slice = 1;
+    if (nt == 0) nt = 256;
     const size_t budget = std::min<size_t>(max_lds, 64 * 1024) - sable::kScratchBytes;
     int g = 4;
     while (g <= 64 && (size_t)(nt / g) * t->wstride * tsz > budget) g <<= 1;
@@ -247,38 +320,12 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     t->gmin = g;
     t->lds_bytes = sable::kScratchBytes + (size_t)(nt / g) * t->wstride * tsz;
   }
+  t->nt = nt;
 
-  // ---- device symbolic data
-  std::vector<int32_t> ord_p(S.n_bus, -1), ord_q(S.n_bus, -1);
-  int np = 0, nq = 0;
-  for (int i = 0; i < S.n_bus; ++i) {
-    if (S.bus_type[i] != PF_BUS_SLACK) ord_p[i] = np++;
-    if (S.bus_type[i] == PF_BUS_PQ) ord_q[i] = nq++;
-  }
-  Packer pk;
-  const size_t o_bt = pk.add(S.bus_type), o_bb = pk.add(S.bus_blk), o_blb = pk.add(S.blk_bus);
-  const size_t o_op = pk.add(ord_p), o_oq = pk.add(ord_q);
-  const size_t o_yrp = pk.add(S.y_rp), o_yci = pk.add(S.y_ci), o_ytr = pk.add(S.y_tr);
-  const size_t o_yg = pk.add(S.y_g), o_yb = pk.add(S.y_b);
-  const size_t o_rp = pk.add(S.rp), o_ci = pk.add(S.ci), o_dg = pk.add(S.diag);
-  const size_t o_mi = pk.add(S.mirror), o_src = pk.add(S.lu_src);
-  const size_t o_us = pk.add(S.upd_start), o_ut = pk.add(S.upd_tgt);
-  const size_t o_llp = pk.add(S.lev_l_ptr), o_llr = pk.add(S.lev_l_rows);
-  const size_t o_lup = pk.add(S.lev_u_ptr), o_lur = pk.add(S.lev_u_rows);
   he = hipMalloc(&t->d_sym, pk.buf.size());
   if (he != hipSuccess) { delete t; return fail(PF_ENOMEM, "pf_template_build: device allocation (pattern)"); }
   he = hipMemcpy(t->d_sym, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
   if (he != hipSuccess) { pf_template_destroy(t); return hip_fail(he, "pf_template_build: upload"); }
-  auto I = [&](size_t o) { return reinterpret_cast<const int*>(static_cast<char*>(t->d_sym) + o); };
-  auto D = [&](size_t o) { return reinterpret_cast<const double*>(static_cast<char*>(t->d_sym) + o); };
-  sable::DevSym& d = t->ds;
-  d.n_bus = S.n_bus; d.nb = S.nb; d.nnzb = S.nnzb(); d.nj = S.nb + S.n_pq; d.npq = S.n_pq;
-  d.npvpq = S.nb; d.nlev_l = S.n_levels_l(); d.nlev_u = S.n_levels_u();
-  d.bus_type = I(o_bt); d.bus_blk = I(o_bb); d.blk_bus = I(o_blb); d.ord_p = I(o_op); d.ord_q = I(o_oq);
-  d.y_rp = I(o_yrp); d.y_ci = I(o_yci); d.y_tr = I(o_ytr); d.y_g = D(o_yg); d.y_b = D(o_yb);
-  d.rp = I(o_rp); d.ci = I(o_ci); d.diag = I(o_dg); d.mirror = I(o_mi); d.lu_src = I(o_src);
-  d.upd_start = I(o_us); d.upd_tgt = I(o_ut);
-  d.lev_l_ptr = I(o_llp); d.lev_l_rows = I(o_llr); d.lev_u_ptr = I(o_lup); d.lev_u_rows = I(o_lur);
 
   // ---- per-scenario workspace for the whole batch
   const size_t bd = (size_t)batch * t->lay.sd * 8, bt = (size_t)batch * t->lay.st * tsz,
@@ -306,6 +353,7 @@ int pf_template_info(const pf_template* t, pf_template_stats* out) {
   out->lds_resident = t->lds_res ? 1 : 0;
   out->block_threads = t->nt;
   out->lds_bytes = (int32_t)t->lds_bytes;
+  out->slice_width = t->slice;
   return PF_OK;
 }
 
@@ -313,11 +361,11 @@ int pf_template_destroy(pf_template* t) {
   g_err.clear();
   if (!t) return PF_OK;
   DeviceGuard g(t->device);
-  hipDeviceSynchronize();
-  if (t->d_sym) hipFree(t->d_sym);
-  if (t->ws_d) hipFree(t->ws_d);
-  if (t->ws_t) hipFree(t->ws_t);
-  if (t->ws_i) hipFree(t->ws_i);
+  (void)hipDeviceSynchronize();
+  if (t->d_sym) (void)hipFree(t->d_sym);
+  if (t->ws_d) (void)hipFree(t->ws_d);
+  if (t->ws_t) (void)hipFree(t->ws_t);
+  if (t->ws_i) (void)hipFree(t->ws_i);
   delete t;
   return PF_OK;
 }
@@ -334,7 +382,8 @@ int pf_solve_batch(pf_template* t, const double* pd, const double* qd, const dou
   kp.pd = pd; kp.qd = qd; kp.pg = pg; kp.vset = vset;
   kp.vm_out = vm; kp.va_out = va;
   kp.iters_out = iters; kp.status_out = status; kp.fnorm_out = final_mismatch;
-  hipError_t he = sable::launch_newton(kp, t->fp32, t->batch, t->nt, t->lds_bytes, t->lds_res,
+  const int grid = (t->batch + t->slice - 1) / t->slice;
+  hipError_t he = sable::launch_newton(kp, t->fp32, t->slice, grid, t->nt, t->lds_bytes, t->lds_res,
                                        static_cast<hipStream_t>(hip_stream));
   if (he != hipSuccess) return hip_fail(he, "pf_solve_batch: launch");
   t->have_factors = t->opt.keep_factors != 0;
@@ -373,21 +422,22 @@ int pf_eval_batch(pf_template* t, int32_t mode, int32_t count, const double* pd,
   kp.rhs = rhs; kp.out = out; kp.count = count;
   t->have_factors = false;   // the evaluation reuses the workspace
   hipError_t he;
+  const int grid = (count + t->slice - 1) / t->slice;
   switch (mode) {
     case PF_EVAL_MISMATCH:
       kp.mode = sable::MODE_EVAL_MISMATCH;
-      he = sable::launch_newton(kp, t->fp32, count, t->nt, t->lds_bytes, t->lds_res, st);
+      he = sable::launch_newton(kp, t->fp32, t->slice, grid, t->nt, t->lds_bytes, t->lds_res, st);
       break;
     case PF_EVAL_STEP:
       kp.mode = sable::MODE_EVAL_STEP;
-      he = sable::launch_newton(kp, t->fp32, count, t->nt, t->lds_bytes, t->lds_res, st);
+      he = sable::launch_newton(kp, t->fp32, t->slice, grid, t->nt, t->lds_bytes, t->lds_res, st);
       break;
     case PF_EVAL_JACOBIAN:
       he = sable::launch_jacobian_dense(kp, count, st);
       break;
     case PF_EVAL_ADJOINT:
       kp.mode = sable::MODE_EVAL_FACTOR;
-      he = sable::launch_newton(kp, t->fp32, count, t->nt, t->lds_bytes, t->lds_res, st);
+      he = sable::launch_newton(kp, t->fp32, t->slice, grid, t->nt, t->lds_bytes, t->lds_res, st);
       if (he == hipSuccess) {
         kp.mode = sable::MODE_EVAL_ADJOINT;
         he = sable::launch_adjoint(kp, t->fp32, count, t->nt, st);

@@ -17,25 +17,36 @@ enum Mode : int {
   MODE_EVAL_ADJOINT = 4,   // adjoint solve with a given right-hand side
 };
 
-// LDS scratch at the start of every kernel's dynamic LDS
-constexpr int kRedBytes = 8 * 32;            // per-wave partial maxima
-constexpr int kFlagInts = 64;                // per-wave flags + zero-pivot flag
-constexpr int kZeroPivotFlag = 32;
-constexpr int kScratchBytes = kRedBytes + 4 * kFlagInts;
+// LDS scratch at the start of every kernel's dynamic LDS: per-(wave,
+// scenario) partial maxima and flags, per-scenario zero-pivot flags.
+constexpr int kMaxWaves = 16;
+constexpr int kMaxSlice = 8;
+constexpr int kRedOff = 0;                                     // double [16][8]
+constexpr int kFlagOff = kRedOff + 8 * kMaxWaves * kMaxSlice;  // int [16][8]
+constexpr int kPivOff = kFlagOff + 4 * kMaxWaves * kMaxSlice;  // int [8]
+constexpr int kScratchBytes = 2048;
 
-// Symbolic arrays on the device (one allocation, see pf_api.cpp).
-struct DevSym {
-  int n_bus, nb, nnzb, nj, npq, npvpq, nlev_l, nlev_u;
-  const int *bus_type, *bus_blk, *blk_bus, *ord_p, *ord_q;
-  const int *y_rp, *y_ci, *y_tr;
-  const double *y_g, *y_b;
-  const int *rp, *ci, *diag, *mirror, *lu_src, *upd_start, *upd_tgt;
-  const int *lev_l_ptr, *lev_l_rows, *lev_u_ptr, *lev_u_rows;
+// Byte offsets of the symbolic arrays inside one packed image (device
+// memory; the prefix [0, newton_bytes) is what the Newton kernel reads and is
+// copied whole into LDS when the slice of a workgroup is LDS-resident).
+struct SymOffsets {
+  int bus_type, bus_blk, blk_bus, y_rp, y_ci, y_g, y_b;
+  int rp, ci, diag, lu_src, upd_start, upd_tgt;
+  int lev_l_ptr, lev_l_rows, lev_u_ptr, lev_u_rows;
+  int newton_bytes;
+  int mirror, y_tr, ord_p, ord_q;
+  int total_bytes;
 };
 
-// Offsets of the per-scenario arrays.  FP64 arrays (in units of double):
+struct Dims {
+  int n_bus, nb, nnzb, nj, npq, npvpq, nlev_l, nlev_u;
+};
+
+// Offsets of the per-scenario arrays, in elements.  FP64 arrays:
 // e f vm va ire iim ps qs dvr dvi aux [n_bus], F dx rr [2 nb].  Factor-
-// precision arrays (units of T): y [2 nb], lu [4 nnzb], dinv [4 nb].
+// precision arrays (T): y [2 nb], lu [4 nnzb], dinv [4 nb].  In an
+// LDS-resident slice of S scenarios every array is interleaved by scenario
+// (element k of scenario s at k*S + s) and starts at offset*S.
 struct StateLayout {
   int o_e, o_f, o_vm, o_va, o_ire, o_iim, o_ps, o_qs, o_dvr, o_dvi, o_aux, o_F, o_dx, o_rr;
   int sd;  // doubles per scenario
@@ -44,8 +55,11 @@ struct StateLayout {
 };
 
 struct KParams {
-  DevSym s;
-  StateLayout lay;
+  Dims dims;
+  SymOffsets so;
+  const unsigned char* sym;  // packed symbolic image (device)
+  StateLayout lay;           // per-scenario layout of the HBM workspace
+  StateLayout llay;          // per-scenario layout inside an LDS-resident slice
   double* ws_d;
   void* ws_t;
   int* ws_i;
@@ -56,8 +70,9 @@ struct KParams {
   int *iters_out, *status_out;
 };
 
-hipError_t launch_newton(const KParams& kp, bool fp32, int grid, int nt, size_t lds, bool lds_res,
-                         hipStream_t st);
+// slice = scenarios per workgroup (1, 2, 4 or 8); slice > 1 needs lds_res.
+hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds,
+                         bool lds_res, hipStream_t st);
 hipError_t launch_adjoint(const KParams& kp, bool fp32, int grid, int nt, hipStream_t st);
 hipError_t launch_jacobian_dense(const KParams& kp, int grid, hipStream_t st);
 hipError_t set_lds_limits(size_t max_lds);

@@ -1,13 +1,21 @@
 // Device kernels of the batched Newton power flow for CDNA4 (gfx950).
 //
-// One workgroup owns one scenario for the whole Newton solve (no host round
-// trip per iteration): complex Y_bus SpMV + mismatch, convergence test,
-// Jacobian value evaluation fused into a row-oriented 2x2-block LU
-// refactorisation on the fixed symbolic pattern (forward solve fused), the
-// level-scheduled backward solve, FP64-residual refinement in the mixed
-// precision mode, and the state update.  Small grids keep every per-scenario
-// array in LDS; large grids keep them in the per-scenario HBM workspace and
-// stage only the row being factorised in LDS.
+// One workgroup owns a slice of S scenarios (S = 1, 2, 4 or 8) for the whole
+// Newton solve, with no host round trip per iteration: complex Y_bus SpMV +
+// mismatch, per-scenario convergence test, Jacobian value evaluation
+// (Algorithm 1) fused into a row-oriented 2x2-block LU refactorisation on the
+// fixed symbolic pattern (forward solve fused), the level-scheduled backward
+// solve, FP64-residual refinement in the mixed-precision mode, and the state
+// update.  Converged scenarios of a slice freeze while the others continue.
+//
+// Two residency modes:
+//  * LDS-resident (small grids): the symbolic image and the whole state of
+//    the S scenarios live in LDS; arrays are interleaved by scenario, so a
+//    lane's scenario index is its lane index modulo S and the S lanes that
+//    share an index load or update adjacent LDS words.
+//  * HBM-resident (large grids, S = 1): the state lives in the scenario's
+//    HBM workspace, the symbolic arrays are read from the shared image (L2),
+//    and only the factor row under elimination is staged in LDS.
 #include "pf_kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -16,8 +24,6 @@ namespace sable {
 
 // ----------------------------------------------------------------------------
 // small helpers
-
-struct B4d { double v[4]; };
 
 template <typename T>
 struct Blk { T a, b, c, d; };  // row-major 2x2 block [[a, b], [c, d]]
@@ -32,275 +38,317 @@ __device__ __forceinline__ Blk<T> mul(const Blk<T>& x, const Blk<T>& y) {
   return {x.a * y.a + x.b * y.c, x.a * y.b + x.b * y.d, x.c * y.a + x.d * y.c, x.c * y.b + x.d * y.d};
 }
 
-// Jacobian entries of J1 = dF1/dz1 for the bus pair (i, m): rows (dP_i, dQ_i),
-// columns (theta_m, |V|_m).  Written in rectangular coordinates V = e + jf,
-// I = Y V: for i != m the products |V_i||V_m| cos(theta_im) = e_i e_m + f_i f_m
-// and |V_i||V_m| sin(theta_im) = f_i e_m - e_i f_m replace the trigonometric
-// terms; the values equal the closed forms of Algorithm 1.
-__device__ __forceinline__ B4d jac_entries(int i, int m, double G, double B, const double* e,
-                                           const double* f, const double* vm, const double* ire,
-                                           const double* iim) {
-  B4d r;
-  if (i == m) {
-    double ei = e[i], fi = f[i], v = vm[i];
-    double P = ei * ire[i] + fi * iim[i];
-    double Q = fi * ire[i] - ei * iim[i];
-    double v2 = v * v;
-    r.v[0] = Q + B * v2;
-    r.v[1] = -P / v - G * v;
-    r.v[2] = -P + G * v2;
-    r.v[3] = -Q / v + B * v;
-  } else {
-    double cc = e[i] * e[m] + f[i] * f[m];
-    double ss = f[i] * e[m] - e[i] * f[m];
-    double gs_bc = G * ss - B * cc;
-    double gc_bs = G * cc + B * ss;
-    double vmm = vm[m];
-    r.v[0] = -gs_bc;
-    r.v[1] = -gc_bs / vmm;
-    r.v[2] = gc_bs;
-    r.v[3] = -gs_bc / vmm;
-  }
-  return r;
+// interleaved indexing inside a slice of S scenarios
+template <int S> __device__ __forceinline__ int sI(int i, int s) { return i * S + s; }
+template <int S> __device__ __forceinline__ int sP(int a, int s) { return (a * S + s) * 2; }
+template <int S> __device__ __forceinline__ int sB(int p, int s) { return (p * S + s) * 4; }
+
+// symbolic arrays, bound to LDS or to the device image
+struct Sym {
+  const int *bus_type, *bus_blk, *blk_bus, *y_rp, *y_ci;
+  const double *y_g, *y_b;
+  const int *rp, *ci, *diag, *lu_src, *upd_start, *upd_tgt;
+  const int *lev_l_ptr, *lev_l_rows, *lev_u_ptr, *lev_u_rows;
+  const int *mirror, *y_tr, *ord_p, *ord_q;
+};
+
+__device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned char* g,
+                                        const SymOffsets& o) {
+  Sym m;
+  m.bus_type = reinterpret_cast<const int*>(nb + o.bus_type);
+  m.bus_blk = reinterpret_cast<const int*>(nb + o.bus_blk);
+  m.blk_bus = reinterpret_cast<const int*>(nb + o.blk_bus);
+  m.y_rp = reinterpret_cast<const int*>(nb + o.y_rp);
+  m.y_ci = reinterpret_cast<const int*>(nb + o.y_ci);
+  m.y_g = reinterpret_cast<const double*>(nb + o.y_g);
+  m.y_b = reinterpret_cast<const double*>(nb + o.y_b);
+  m.rp = reinterpret_cast<const int*>(nb + o.rp);
+  m.ci = reinterpret_cast<const int*>(nb + o.ci);
+  m.diag = reinterpret_cast<const int*>(nb + o.diag);
+  m.lu_src = reinterpret_cast<const int*>(nb + o.lu_src);
+  m.upd_start = reinterpret_cast<const int*>(nb + o.upd_start);
+  m.upd_tgt = reinterpret_cast<const int*>(nb + o.upd_tgt);
+  m.lev_l_ptr = reinterpret_cast<const int*>(nb + o.lev_l_ptr);
+  m.lev_l_rows = reinterpret_cast<const int*>(nb + o.lev_l_rows);
+  m.lev_u_ptr = reinterpret_cast<const int*>(nb + o.lev_u_ptr);
+  m.lev_u_rows = reinterpret_cast<const int*>(nb + o.lev_u_rows);
+  m.mirror = reinterpret_cast<const int*>(g + o.mirror);
+  m.y_tr = reinterpret_cast<const int*>(g + o.y_tr);
+  m.ord_p = reinterpret_cast<const int*>(g + o.ord_p);
+  m.ord_q = reinterpret_cast<const int*>(g + o.ord_q);
+  return m;
 }
 
-// The 2x2 block of the padded block system at LU position p of block row a.
-// PV buses keep a dummy |V| unknown and a dummy dQ row: identity on the
-// diagonal, zero coupling; fill-in positions start at zero.
+// per-slice state; element k of scenario s sits at k*S + s
 template <typename T>
-__device__ __forceinline__ Blk<T> fill_block(const DevSym& s, int a, int p, const double* e,
-                                             const double* f, const double* vm, const double* ire,
-                                             const double* iim) {
-  const int src = s.lu_src[p];
-  const int j = s.ci[p];
+struct St {
+  double *e, *f, *vm, *va, *ire, *iim, *ps, *qs, *dvr, *dvi, *aux, *F, *dx, *rr;
+  T *y, *lu, *dinv;
+};
+
+template <typename T, int S>
+__device__ __forceinline__ St<T> bind_state(double* d, T* t, const StateLayout& L) {
+  St<T> c;
+  c.e = d + L.o_e * S; c.f = d + L.o_f * S; c.vm = d + L.o_vm * S; c.va = d + L.o_va * S;
+  c.ire = d + L.o_ire * S; c.iim = d + L.o_iim * S; c.ps = d + L.o_ps * S; c.qs = d + L.o_qs * S;
+  c.dvr = d + L.o_dvr * S; c.dvi = d + L.o_dvi * S; c.aux = d + L.o_aux * S;
+  c.F = d + L.o_F * S; c.dx = d + L.o_dx * S; c.rr = d + L.o_rr * S;
+  c.y = t + L.o_y * S; c.lu = t + L.o_lu * S; c.dinv = t + L.o_dinv * S;
+  return c;
+}
+
+// Jacobian entries of J1 = dF1/dz1 for the bus pair (i, m): rows (dP_i, dQ_i),
+// columns (theta_m, |V|_m), in rectangular coordinates V = e + jf, I = Y V.
+// For i != m the products |V_i||V_m| cos(theta_im) = e_i e_m + f_i f_m and
+// |V_i||V_m| sin(theta_im) = f_i e_m - e_i f_m replace the trigonometric
+// terms; the values equal the closed forms of Algorithm 1.
+struct J4 { double v[4]; };
+
+__device__ __forceinline__ J4 jac_diag(double G, double B, double ei, double fi, double vmi,
+                                       double iri, double iii) {
+  const double P = ei * iri + fi * iii;
+  const double Q = fi * iri - ei * iii;
+  const double v2 = vmi * vmi;
+  return {{Q + B * v2, -P / vmi - G * vmi, -P + G * v2, -Q / vmi + B * vmi}};
+}
+
+__device__ __forceinline__ J4 jac_off(double G, double B, double ei, double fi, double em, double fm,
+                                      double vmm) {
+  const double cc = ei * em + fi * fm;
+  const double ss = fi * em - ei * fm;
+  const double gs_bc = G * ss - B * cc;
+  const double gc_bs = G * cc + B * ss;
+  return {{-gs_bc, -gc_bs / vmm, gc_bs, -gs_bc / vmm}};
+}
+
+// The 2x2 block of the padded block system at LU position p of block row a
+// for scenario s.  PV buses keep a dummy |V| unknown and a dummy dQ row:
+// identity on the diagonal, zero coupling; fill-in positions start at zero.
+template <typename T, int S>
+__device__ __forceinline__ Blk<T> fill_block(const Sym& m, const St<T>& c, int a, int p, int s) {
+  const int src = m.lu_src[p];
+  const int j = m.ci[p];
   const bool dg = (j == a);
   if (src < 0 && !dg) return {T(0), T(0), T(0), T(0)};
-  const int i = s.blk_bus[a], m = s.blk_bus[j];
-  const double G = src < 0 ? 0.0 : s.y_g[src];
-  const double Bv = src < 0 ? 0.0 : s.y_b[src];
-  B4d x = jac_entries(i, m, G, Bv, e, f, vm, ire, iim);
-  const bool pv_i = s.bus_type[i] == 1, pv_m = s.bus_type[m] == 1;
+  const int i = m.blk_bus[a], mm = m.blk_bus[j];
+  const double G = src < 0 ? 0.0 : m.y_g[src];
+  const double Bv = src < 0 ? 0.0 : m.y_b[src];
+  const int is = sI<S>(i, s);
+  J4 x = dg ? jac_diag(G, Bv, c.e[is], c.f[is], c.vm[is], c.ire[is], c.iim[is])
+            : jac_off(G, Bv, c.e[is], c.f[is], c.e[sI<S>(mm, s)], c.f[sI<S>(mm, s)], c.vm[sI<S>(mm, s)]);
+  const bool pv_i = m.bus_type[i] == 1, pv_m = m.bus_type[mm] == 1;
   if (pv_i) { x.v[2] = 0.0; x.v[3] = 0.0; }
   if (pv_m) { x.v[1] = 0.0; x.v[3] = 0.0; }
   if (dg && pv_i) x.v[3] = 1.0;
   return {T(x.v[0]), T(x.v[1]), T(x.v[2]), T(x.v[3])};
 }
 
+// lanes per row group: enough groups for the rows of a level, at least S
+// lanes (one per scenario of the slice), at least gmin (HBM workspace limit)
 __device__ __forceinline__ int pick_group(int nrows, int nt, int gmin) {
   int g = 64;
   while (g > gmin && (nt / g) < nrows) g >>= 1;
   return g;
 }
 
-template <typename T>
+// sum over the G/S entry lanes of one scenario inside a group
+template <typename T, int S>
 __device__ __forceinline__ T group_sum(T v, int G) {
-  for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  for (int o = G >> 1; o >= S; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
 
-// ----------------------------------------------------------------------------
-// per-scenario context: pointers into LDS or into the HBM workspace
-
-template <typename T>
-struct Ctx {
-  double *e, *f, *vm, *va, *ire, *iim, *ps, *qs, *dvr, *dvi, *aux;  // [n_bus]
-  double *F, *dx, *rr;                                        // [2 nb]
-  T *y;                                                       // [2 nb]
-  T *lu, *dinv;                                               // [4 nnzb], [4 nb]
-  T *wsp;                                                     // row workspaces (HBM mode)
-  double* red;                                                // [nwaves]
-  int* flags;                                                 // [nwaves + 4]
-};
-
-template <typename T>
-__device__ void bind_state(Ctx<T>& c, double* d, T* t, const StateLayout& L) {
-  c.e = d + L.o_e; c.f = d + L.o_f; c.vm = d + L.o_vm; c.va = d + L.o_va;
-  c.ire = d + L.o_ire; c.iim = d + L.o_iim; c.ps = d + L.o_ps; c.qs = d + L.o_qs;
-  c.dvr = d + L.o_dvr; c.dvi = d + L.o_dvi; c.aux = d + L.o_aux;
-  c.F = d + L.o_F; c.dx = d + L.o_dx; c.rr = d + L.o_rr;
-  c.y = t + L.o_y; c.lu = t + L.o_lu; c.dinv = t + L.o_dinv;
-}
-
-// max over the workgroup of v, OR of bad; every thread gets the result
-__device__ double block_max(double v, int bad, int* bad_out, double* red, int* flags, int tid, int nt) {
-  for (int o = 32; o > 0; o >>= 1) {
+// per-scenario max over the workgroup of v and OR of bad (thread's scenario
+// is tid % S); every thread receives all S results
+template <int S>
+__device__ void block_max(double v, int bad, double* fn, int* bd, unsigned char* scr, int tid, int nt) {
+  double* red = reinterpret_cast<double*>(scr + kRedOff);
+  int* flg = reinterpret_cast<int*>(scr + kFlagOff);
+  for (int o = 32; o >= S; o >>= 1) {
     v = fmax(v, __shfl_xor(v, o));
     bad |= __shfl_xor(bad, o);
   }
-  const int w = tid >> 6;
-  if ((tid & 63) == 0) { red[w] = v; flags[w] = bad; }
+  const int w = tid >> 6, l = tid & 63;
+  if (l < S) { red[w * S + l] = v; flg[w * S + l] = bad; }
   __syncthreads();
-  double m = 0.0;
-  int b = 0;
-  for (int k = 0; k < (nt >> 6); ++k) { m = fmax(m, red[k]); b |= flags[k]; }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    double mx = 0.0;
+    int b = 0;
+    for (int k = 0; k < (nt >> 6); ++k) { mx = fmax(mx, red[k * S + s]); b |= flg[k * S + s]; }
+    fn[s] = mx;
+    bd[s] = b;
+  }
   __syncthreads();
-  *bad_out = b;
-  return m;
 }
 
 // ----------------------------------------------------------------------------
 // phases (each ends with a workgroup barrier)
 
-// I = Y V, S = V conj(I), F1 = spec - calc on the block rows; returns ||F1||_inf.
-template <typename T>
-__device__ double phase_mismatch(const DevSym& s, Ctx<T>& c, int tid, int nt, int* bad_out) {
+// I = Y V, S = V conj(I), F1 = spec - calc on the block rows; ||F1||_inf per scenario.
+template <typename T, int S>
+__device__ void phase_mismatch(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, double* fn,
+                               int* bd, unsigned char* scr) {
   double mx = 0.0;
   int bad = 0;
-  for (int i = tid; i < s.n_bus; i += nt) {
+  const int s = tid % S;
+  for (int idx = tid; idx < D.n_bus * S; idx += nt) {
+    const int i = idx / S;
     double ir = 0.0, ii = 0.0;
-    for (int q = s.y_rp[i]; q < s.y_rp[i + 1]; ++q) {
-      const int j = s.y_ci[q];
-      const double g = s.y_g[q], b = s.y_b[q];
-      const double ej = c.e[j], fj = c.f[j];
+    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
+      const int j = m.y_ci[q];
+      const double g = m.y_g[q], b = m.y_b[q];
+      const double ej = c.e[sI<S>(j, s)], fj = c.f[sI<S>(j, s)];
       ir += g * ej - b * fj;
       ii += g * fj + b * ej;
     }
-    c.ire[i] = ir;
-    c.iim[i] = ii;
-    const int a = s.bus_blk[i];
+    c.ire[idx] = ir;
+    c.iim[idx] = ii;
+    const int a = m.bus_blk[i];
     if (a >= 0) {
-      const double ei = c.e[i], fi = c.f[i];
+      const double ei = c.e[idx], fi = c.f[idx];
       const double P = ei * ir + fi * ii;
       const double Q = fi * ir - ei * ii;
-      const double F0 = c.ps[i] - P;
-      const double F1 = s.bus_type[i] == 0 ? c.qs[i] - Q : 0.0;
-      c.F[2 * a] = F0;
-      c.F[2 * a + 1] = F1;
+      const double F0 = c.ps[idx] - P;
+      const double F1 = m.bus_type[i] == 0 ? c.qs[idx] - Q : 0.0;
+      c.F[sP<S>(a, s)] = F0;
+      c.F[sP<S>(a, s) + 1] = F1;
       bad |= !(isfinite(F0) && isfinite(F1));
       mx = fmax(mx, fmax(fabs(F0), fabs(F1)));
     }
   }
   __syncthreads();
-  return block_max(mx, bad, bad_out, c.red, c.flags, tid, nt);
+  block_max<S>(mx, bad, fn, bd, scr, tid, nt);
 }
 
-// Row-oriented block LU of one row (Doolittle by rows): fill the row's J1
-// values, eliminate it against the finished rows k in L(a,:) in increasing
-// order (L_ak = A_ak U_kk^-1; A_aj -= L_ak U_kj for j in U(k,>k)), apply the
-// same L_ak to the right-hand side (forward solve), and invert the pivot
-// block.  The G lanes of one group share the row; all of them belong to one
-// wavefront, whose LDS operations complete in program order, so a value one
-// lane writes in step k is seen by every lane in step k+1.
-template <typename T, bool LDS>
-__device__ void factor_row(const DevSym& s, Ctx<T>& c, int a, int lane, int G, T* W, bool fill,
-                           bool fwd) {
-  const int rs = s.rp[a], re = s.rp[a + 1], dg = s.diag[a];
+// Row-oriented block LU of one row (Doolittle by rows) for the S scenarios
+// of the slice: fill the row's J1 values, eliminate it against the finished
+// rows k in L(a,:) in increasing order (L_ak = A_ak U_kk^-1; A_aj -= L_ak U_kj
+// for j in U(k,>k)), apply the same L_ak to the right-hand side (forward
+// solve), and invert the pivot block.  The G lanes of a group share the row
+// (lane = scenario + S * entry) and belong to one wavefront, whose LDS
+// operations complete in program order, so a value one lane writes in step k
+// is seen by every lane in step k+1.  W is the row: in place in an
+// LDS-resident slice, a staging copy in LDS otherwise.
+template <typename T, int S, bool RES>
+__device__ void factor_row(const Sym& m, St<T>& c, int a, int l, int G, T* W, bool fill, bool fwd,
+                           int* piv) {
+  const int s = l % S, e = l / S, E = G / S;
+  const int rs = m.rp[a], re = m.rp[a + 1], dg = m.diag[a];
   const int len = re - rs;
   if (fill) {
-    for (int q = lane; q < len; q += G)
-      st_blk(W + 4 * q, fill_block<T>(s, a, rs + q, c.e, c.f, c.vm, c.ire, c.iim));
-  } else if (!LDS) {
-    for (int q = lane; q < len; q += G) st_blk(W + 4 * q, ld_blk(c.lu + 4 * (rs + q)));
+    for (int q = e; q < len; q += E) st_blk(W + sB<S>(q, s), fill_block<T, S>(m, c, a, rs + q, s));
   }
   T y0 = T(0), y1 = T(0);
-  if (fwd) { y0 = c.y[2 * a]; y1 = c.y[2 * a + 1]; }
+  if (fwd) { y0 = c.y[sP<S>(a, s)]; y1 = c.y[sP<S>(a, s) + 1]; }
   for (int p = rs; p < dg; ++p) {
-    const int k = s.ci[p];
+    const int k = m.ci[p];
     const int q = p - rs;
-    const Blk<T> A = ld_blk(W + 4 * q);
-    const Blk<T> L = mul(A, ld_blk(c.dinv + 4 * k));
+    const Blk<T> L = mul(ld_blk(W + sB<S>(q, s)), ld_blk(c.dinv + sB<S>(k, s)));
     if (fwd) {
-      const T yk0 = c.y[2 * k], yk1 = c.y[2 * k + 1];
+      const T yk0 = c.y[sP<S>(k, s)], yk1 = c.y[sP<S>(k, s) + 1];
       y0 -= L.a * yk0 + L.b * yk1;
       y1 -= L.c * yk0 + L.d * yk1;
     }
-    const int ks = s.diag[k] + 1;
-    const int n = s.rp[k + 1] - ks;
-    const int ts = s.upd_start[p];
-    for (int t = lane; t < n; t += G) {
-      const Blk<T> U = ld_blk(c.lu + 4 * (ks + t));
-      T* w = W + 4 * s.upd_tgt[ts + t];
+    const int ks = m.diag[k] + 1;
+    const int n = m.rp[k + 1] - ks;
+    const int ts = m.upd_start[p];
+    for (int t = e; t < n; t += E) {
+      const Blk<T> U = ld_blk(c.lu + sB<S>(ks + t, s));
+      T* w = W + sB<S>(m.upd_tgt[ts + t], s);
       Blk<T> x = ld_blk(w);
       const Blk<T> LU = mul(L, U);
       x.a -= LU.a; x.b -= LU.b; x.c -= LU.c; x.d -= LU.d;
       st_blk(w, x);
     }
-    if (lane == 0) st_blk(W + 4 * q, L);
+    if (e == 0) st_blk(W + sB<S>(q, s), L);
   }
-  if (lane == 0) {
-    const Blk<T> D = ld_blk(W + 4 * (dg - rs));
-    const T det = D.a * D.d - D.b * D.c;
+  if (e == 0) {
+    const Blk<T> Dk = ld_blk(W + sB<S>(dg - rs, s));
+    const T det = Dk.a * Dk.d - Dk.b * Dk.c;
     const T inv = T(1) / det;
-    const Blk<T> Di = {D.d * inv, -D.b * inv, -D.c * inv, D.a * inv};
+    const Blk<T> Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
     // pivots of the block: a, then the Schur complement d - c b / a
-    const T p1 = D.a, p2 = det / D.a;
+    const T p1 = Dk.a, p2 = det / Dk.a;
     const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
-    const bool zero = !(fabs(p1) > eps * (fabs(D.a) + fabs(D.b))) ||
-                      !(fabs(p2) > eps * (fabs(D.c) + fabs(D.d))) || !isfinite(inv);
-    if (zero) c.flags[kZeroPivotFlag] = 1;
-    st_blk(c.dinv + 4 * a, Di);
-    if (fwd) { c.y[2 * a] = y0; c.y[2 * a + 1] = y1; }
+    const bool zero = !(fabs(p1) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
+                      !(fabs(p2) > eps * (fabs(Dk.c) + fabs(Dk.d))) || !isfinite(inv);
+    if (zero) piv[s] = 1;
+    st_blk(c.dinv + sB<S>(a, s), Di);
+    if (fwd) { c.y[sP<S>(a, s)] = y0; c.y[sP<S>(a, s) + 1] = y1; }
   }
-  if (!LDS) {
-    for (int q = lane; q < len; q += G) st_blk(c.lu + 4 * (rs + q), ld_blk(W + 4 * q));
+  if (!RES) {
+    for (int q = e; q < len; q += E) st_blk(c.lu + sB<S>(rs + q, s), ld_blk(W + sB<S>(q, s)));
   }
 }
 
-template <typename T, bool LDS>
-__device__ void phase_factor(const DevSym& s, Ctx<T>& c, int tid, int nt, int gmin, int wstride,
-                             bool fill, bool fwd) {
-  for (int lev = 0; lev < s.nlev_l; ++lev) {
-    const int r0 = s.lev_l_ptr[lev], r1 = s.lev_l_ptr[lev + 1];
+template <typename T, int S, bool RES>
+__device__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, T* wsp, int tid, int nt,
+                             int gmin, int wstride, bool fill, bool fwd, int* piv) {
+  for (int lev = 0; lev < D.nlev_l; ++lev) {
+    const int r0 = m.lev_l_ptr[lev], r1 = m.lev_l_ptr[lev + 1];
     const int G = pick_group(r1 - r0, nt, gmin);
     const int gid = tid / G, lane = tid % G, ng = nt / G;
     for (int ri = r0 + gid; ri < r1; ri += ng) {
-      const int a = s.lev_l_rows[ri];
-      T* W = LDS ? c.lu + 4 * s.rp[a] : c.wsp + (size_t)gid * wstride;
-      factor_row<T, LDS>(s, c, a, lane, G, W, fill, fwd);
+      const int a = m.lev_l_rows[ri];
+      T* W = RES ? c.lu + sB<S>(m.rp[a], 0) : wsp + (size_t)gid * wstride;
+      factor_row<T, S, RES>(m, c, a, lane, G, W, fill, fwd, piv);
     }
     __syncthreads();
   }
 }
 
 // L y = y (unit block-lower, in place) by L-levels
-template <typename T>
-__device__ void phase_fsolve(const DevSym& s, Ctx<T>& c, int tid, int nt, int gmin) {
-  for (int lev = 0; lev < s.nlev_l; ++lev) {
-    const int r0 = s.lev_l_ptr[lev], r1 = s.lev_l_ptr[lev + 1];
+template <typename T, int S>
+__device__ void phase_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
+  for (int lev = 0; lev < D.nlev_l; ++lev) {
+    const int r0 = m.lev_l_ptr[lev], r1 = m.lev_l_ptr[lev + 1];
     const int G = pick_group(r1 - r0, nt, gmin);
     const int gid = tid / G, lane = tid % G, ng = nt / G;
+    const int s = lane % S, e = lane / S, E = G / S;
     for (int ri = r0 + gid; ri < r1; ri += ng) {
-      const int a = s.lev_l_rows[ri];
+      const int a = m.lev_l_rows[ri];
       T s0 = T(0), s1 = T(0);
-      for (int p = s.rp[a] + lane; p < s.diag[a]; p += G) {
-        const Blk<T> L = ld_blk(c.lu + 4 * p);
-        const int k = s.ci[p];
-        const T y0 = c.y[2 * k], y1 = c.y[2 * k + 1];
+      for (int p = m.rp[a] + e; p < m.diag[a]; p += E) {
+        const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
+        const int k = m.ci[p];
+        const T y0 = c.y[sP<S>(k, s)], y1 = c.y[sP<S>(k, s) + 1];
         s0 += L.a * y0 + L.b * y1;
         s1 += L.c * y0 + L.d * y1;
       }
-      s0 = group_sum(s0, G);
-      s1 = group_sum(s1, G);
-      if (lane == 0) { c.y[2 * a] -= s0; c.y[2 * a + 1] -= s1; }
+      s0 = group_sum<T, S>(s0, G);
+      s1 = group_sum<T, S>(s1, G);
+      if (e == 0) { c.y[sP<S>(a, s)] -= s0; c.y[sP<S>(a, s) + 1] -= s1; }
     }
     __syncthreads();
   }
 }
 
 // U x = y (block-upper with full diagonal blocks, in place) by U-levels
-template <typename T>
-__device__ void phase_bsolve(const DevSym& s, Ctx<T>& c, int tid, int nt, int gmin) {
-  for (int lev = 0; lev < s.nlev_u; ++lev) {
-    const int r0 = s.lev_u_ptr[lev], r1 = s.lev_u_ptr[lev + 1];
+template <typename T, int S>
+__device__ void phase_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
+  for (int lev = 0; lev < D.nlev_u; ++lev) {
+    const int r0 = m.lev_u_ptr[lev], r1 = m.lev_u_ptr[lev + 1];
     const int G = pick_group(r1 - r0, nt, gmin);
     const int gid = tid / G, lane = tid % G, ng = nt / G;
+    const int s = lane % S, e = lane / S, E = G / S;
     for (int ri = r0 + gid; ri < r1; ri += ng) {
-      const int a = s.lev_u_rows[ri];
+      const int a = m.lev_u_rows[ri];
       T s0 = T(0), s1 = T(0);
-      for (int p = s.diag[a] + 1 + lane; p < s.rp[a + 1]; p += G) {
-        const Blk<T> U = ld_blk(c.lu + 4 * p);
-        const int j = s.ci[p];
-        const T x0 = c.y[2 * j], x1 = c.y[2 * j + 1];
+      for (int p = m.diag[a] + 1 + e; p < m.rp[a + 1]; p += E) {
+        const Blk<T> U = ld_blk(c.lu + sB<S>(p, s));
+        const int j = m.ci[p];
+        const T x0 = c.y[sP<S>(j, s)], x1 = c.y[sP<S>(j, s) + 1];
         s0 += U.a * x0 + U.b * x1;
         s1 += U.c * x0 + U.d * x1;
       }
-      s0 = group_sum(s0, G);
-      s1 = group_sum(s1, G);
-      if (lane == 0) {
-        const Blk<T> D = ld_blk(c.dinv + 4 * a);
-        const T t0 = c.y[2 * a] - s0, t1 = c.y[2 * a + 1] - s1;
-        c.y[2 * a] = D.a * t0 + D.b * t1;
-        c.y[2 * a + 1] = D.c * t0 + D.d * t1;
+      s0 = group_sum<T, S>(s0, G);
+      s1 = group_sum<T, S>(s1, G);
+      if (e == 0) {
+        const Blk<T> Di = ld_blk(c.dinv + sB<S>(a, s));
+        const T t0 = c.y[sP<S>(a, s)] - s0, t1 = c.y[sP<S>(a, s) + 1] - s1;
+        c.y[sP<S>(a, s)] = Di.a * t0 + Di.b * t1;
+        c.y[sP<S>(a, s) + 1] = Di.c * t0 + Di.d * t1;
       }
     }
     __syncthreads();
@@ -309,28 +357,28 @@ __device__ void phase_bsolve(const DevSym& s, Ctx<T>& c, int tid, int nt, int gm
 
 // U^T w = g (in place in y) by L-levels: w_a = U_aa^-T (g_a - sum_k U_ka^T w_k)
 template <typename T>
-__device__ void phase_ut_solve(const DevSym& s, Ctx<T>& c, int tid, int nt, int gmin) {
-  for (int lev = 0; lev < s.nlev_l; ++lev) {
-    const int r0 = s.lev_l_ptr[lev], r1 = s.lev_l_ptr[lev + 1];
+__device__ void phase_ut_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
+  for (int lev = 0; lev < D.nlev_l; ++lev) {
+    const int r0 = m.lev_l_ptr[lev], r1 = m.lev_l_ptr[lev + 1];
     const int G = pick_group(r1 - r0, nt, gmin);
     const int gid = tid / G, lane = tid % G, ng = nt / G;
     for (int ri = r0 + gid; ri < r1; ri += ng) {
-      const int a = s.lev_l_rows[ri];
+      const int a = m.lev_l_rows[ri];
       T s0 = T(0), s1 = T(0);
-      for (int p = s.rp[a] + lane; p < s.diag[a]; p += G) {
-        const Blk<T> U = ld_blk(c.lu + 4 * s.mirror[p]);  // U_ka, k = ci[p]
-        const int k = s.ci[p];
+      for (int p = m.rp[a] + lane; p < m.diag[a]; p += G) {
+        const Blk<T> U = ld_blk(c.lu + 4 * m.mirror[p]);  // U_ka, k = ci[p]
+        const int k = m.ci[p];
         const T w0 = c.y[2 * k], w1 = c.y[2 * k + 1];
         s0 += U.a * w0 + U.c * w1;
         s1 += U.b * w0 + U.d * w1;
       }
-      s0 = group_sum(s0, G);
-      s1 = group_sum(s1, G);
+      s0 = group_sum<T, 1>(s0, G);
+      s1 = group_sum<T, 1>(s1, G);
       if (lane == 0) {
-        const Blk<T> D = ld_blk(c.dinv + 4 * a);
+        const Blk<T> Di = ld_blk(c.dinv + 4 * a);
         const T t0 = c.y[2 * a] - s0, t1 = c.y[2 * a + 1] - s1;
-        c.y[2 * a] = D.a * t0 + D.c * t1;
-        c.y[2 * a + 1] = D.b * t0 + D.d * t1;
+        c.y[2 * a] = Di.a * t0 + Di.c * t1;
+        c.y[2 * a + 1] = Di.b * t0 + Di.d * t1;
       }
     }
     __syncthreads();
@@ -339,23 +387,23 @@ __device__ void phase_ut_solve(const DevSym& s, Ctx<T>& c, int tid, int nt, int 
 
 // L^T l = w (in place in y) by U-levels: l_a = w_a - sum_j L_ja^T l_j
 template <typename T>
-__device__ void phase_lt_solve(const DevSym& s, Ctx<T>& c, int tid, int nt, int gmin) {
-  for (int lev = 0; lev < s.nlev_u; ++lev) {
-    const int r0 = s.lev_u_ptr[lev], r1 = s.lev_u_ptr[lev + 1];
+__device__ void phase_lt_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
+  for (int lev = 0; lev < D.nlev_u; ++lev) {
+    const int r0 = m.lev_u_ptr[lev], r1 = m.lev_u_ptr[lev + 1];
     const int G = pick_group(r1 - r0, nt, gmin);
     const int gid = tid / G, lane = tid % G, ng = nt / G;
     for (int ri = r0 + gid; ri < r1; ri += ng) {
-      const int a = s.lev_u_rows[ri];
+      const int a = m.lev_u_rows[ri];
       T s0 = T(0), s1 = T(0);
-      for (int p = s.diag[a] + 1 + lane; p < s.rp[a + 1]; p += G) {
-        const Blk<T> L = ld_blk(c.lu + 4 * s.mirror[p]);  // L_ja, j = ci[p]
-        const int j = s.ci[p];
+      for (int p = m.diag[a] + 1 + lane; p < m.rp[a + 1]; p += G) {
+        const Blk<T> L = ld_blk(c.lu + 4 * m.mirror[p]);  // L_ja, j = ci[p]
+        const int j = m.ci[p];
         const T l0 = c.y[2 * j], l1 = c.y[2 * j + 1];
         s0 += L.a * l0 + L.c * l1;
         s1 += L.b * l0 + L.d * l1;
       }
-      s0 = group_sum(s0, G);
-      s1 = group_sum(s1, G);
+      s0 = group_sum<T, 1>(s0, G);
+      s1 = group_sum<T, 1>(s1, G);
       if (lane == 0) { c.y[2 * a] -= s0; c.y[2 * a + 1] -= s1; }
     }
     __syncthreads();
@@ -363,47 +411,50 @@ __device__ void phase_lt_solve(const DevSym& s, Ctx<T>& c, int tid, int nt, int 
 }
 
 // dV = V (d|V|/|V| + j dtheta) for the correction dx (slack: 0)
-template <typename T>
-__device__ void phase_dv(const DevSym& s, Ctx<T>& c, int tid, int nt) {
-  for (int i = tid; i < s.n_bus; i += nt) {
-    const int a = s.bus_blk[i];
+template <typename T, int S>
+__device__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+  for (int idx = tid; idx < D.n_bus * S; idx += nt) {
+    const int i = idx / S, s = idx % S;
+    const int a = m.bus_blk[i];
     double dvr = 0.0, dvi = 0.0;
     if (a >= 0) {
-      const double dth = c.dx[2 * a];
-      const double rho = s.bus_type[i] == 0 ? c.dx[2 * a + 1] / c.vm[i] : 0.0;
-      dvr = c.e[i] * rho - c.f[i] * dth;
-      dvi = c.f[i] * rho + c.e[i] * dth;
+      const double dth = c.dx[sP<S>(a, s)];
+      const double rho = m.bus_type[i] == 0 ? c.dx[sP<S>(a, s) + 1] / c.vm[idx] : 0.0;
+      dvr = c.e[idx] * rho - c.f[idx] * dth;
+      dvi = c.f[idx] * rho + c.e[idx] * dth;
     }
-    c.dvr[i] = dvr;
-    c.dvi[i] = dvi;
+    c.dvr[idx] = dvr;
+    c.dvi[idx] = dvi;
   }
   __syncthreads();
 }
 
 // r = -F1 - J1 dx in FP64 without forming J1: J1 dx = -(dS restricted to the
 // F1 rows), dS = dV conj(I) + V conj(Y dV).  Result cast into y.
-template <typename T>
-__device__ void phase_residual(const DevSym& s, Ctx<T>& c, int tid, int nt) {
-  for (int i = tid; i < s.n_bus; i += nt) {
-    const int a = s.bus_blk[i];
+template <typename T, int S>
+__device__ void phase_residual(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+  for (int idx = tid; idx < D.n_bus * S; idx += nt) {
+    const int i = idx / S, s = idx % S;
+    const int a = m.bus_blk[i];
     if (a < 0) continue;
     double dir = 0.0, dii = 0.0;
-    for (int q = s.y_rp[i]; q < s.y_rp[i + 1]; ++q) {
-      const int j = s.y_ci[q];
-      const double g = s.y_g[q], b = s.y_b[q];
+    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
+      const int j = sI<S>(m.y_ci[q], s);
+      const double g = m.y_g[q], b = m.y_b[q];
       dir += g * c.dvr[j] - b * c.dvi[j];
       dii += g * c.dvi[j] + b * c.dvr[j];
     }
-    const double e = c.e[i], f = c.f[i], ir = c.ire[i], ii = c.iim[i];
-    const double dvr = c.dvr[i], dvi = c.dvi[i];
+    const double e = c.e[idx], f = c.f[idx], ir = c.ire[idx], ii = c.iim[idx];
+    const double dvr = c.dvr[idx], dvi = c.dvi[idx];
     const double dSr = dvr * ir + dvi * ii + e * dir + f * dii;
     const double dSi = dvi * ir - dvr * ii + f * dir - e * dii;
-    const double r0 = -c.F[2 * a] + dSr;
-    const double r1 = s.bus_type[i] == 0 ? -c.F[2 * a + 1] + dSi : 0.0;
-    c.rr[2 * a] = r0;
-    c.rr[2 * a + 1] = r1;
-    c.y[2 * a] = T(r0);
-    c.y[2 * a + 1] = T(r1);
+    const int o = sP<S>(a, s);
+    const double r0 = -c.F[o] + dSr;
+    const double r1 = m.bus_type[i] == 0 ? -c.F[o + 1] + dSi : 0.0;
+    c.rr[o] = r0;
+    c.rr[o + 1] = r1;
+    c.y[o] = T(r0);
+    c.y[o + 1] = T(r1);
   }
   __syncthreads();
 }
@@ -413,40 +464,40 @@ __device__ void phase_residual(const DevSym& s, Ctx<T>& c, int tid, int nt) {
 // c_m = conj(nu_m I_m) + sum_i Y_im nu_i conj(V_i),
 //   (J1^T lam)_theta_m = Im(V_m c_m),  (J1^T lam)_|V|m = -Re(V_m c_m) / |V_m|.
 // Also stores Re(V_m c_m) / |V_m| = -(J3^T lam)_m for every bus in aux.
-// g == nullptr: only aux is produced.
+// g == nullptr: only aux is produced.  One scenario (HBM state).
 template <typename T>
-__device__ void phase_adj_residual(const DevSym& s, Ctx<T>& c, int tid, int nt,
+__device__ void phase_adj_residual(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
                                    const double* lam, const double* g, bool to_y) {
-  for (int i = tid; i < s.n_bus; i += nt) {   // w_i = nu_i conj(V_i) -> (dvr, dvi)
-    const int a = s.bus_blk[i];
+  for (int i = tid; i < D.n_bus; i += nt) {   // w_i = nu_i conj(V_i) -> (dvr, dvi)
+    const int a = m.bus_blk[i];
     double nr = 0.0, ni = 0.0;
-    if (a >= 0) { nr = lam[2 * a]; ni = s.bus_type[i] == 0 ? lam[2 * a + 1] : 0.0; }
+    if (a >= 0) { nr = lam[2 * a]; ni = m.bus_type[i] == 0 ? lam[2 * a + 1] : 0.0; }
     c.dvr[i] = nr * c.e[i] + ni * c.f[i];
     c.dvi[i] = ni * c.e[i] - nr * c.f[i];
   }
   __syncthreads();
-  for (int m = tid; m < s.n_bus; m += nt) {
+  for (int mb = tid; mb < D.n_bus; mb += nt) {
     double tr = 0.0, ti = 0.0;
-    for (int q = s.y_rp[m]; q < s.y_rp[m + 1]; ++q) {
-      const int i = s.y_ci[q];
-      const int qt = s.y_tr[q];              // position of Y_im
-      const double yg = s.y_g[qt], yb = s.y_b[qt];
+    for (int q = m.y_rp[mb]; q < m.y_rp[mb + 1]; ++q) {
+      const int i = m.y_ci[q];
+      const int qt = m.y_tr[q];              // position of Y_im
+      const double yg = m.y_g[qt], yb = m.y_b[qt];
       tr += yg * c.dvr[i] - yb * c.dvi[i];
       ti += yg * c.dvi[i] + yb * c.dvr[i];
     }
-    const int a = s.bus_blk[m];
+    const int a = m.bus_blk[mb];
     double nr = 0.0, ni = 0.0;
-    if (a >= 0) { nr = lam[2 * a]; ni = s.bus_type[m] == 0 ? lam[2 * a + 1] : 0.0; }
-    const double ir = c.ire[m], ii = c.iim[m];
+    if (a >= 0) { nr = lam[2 * a]; ni = m.bus_type[mb] == 0 ? lam[2 * a + 1] : 0.0; }
+    const double ir = c.ire[mb], ii = c.iim[mb];
     const double cr = (nr * ir - ni * ii) + tr;      // Re c_m
     const double ci = -(nr * ii + ni * ir) + ti;     // Im c_m
-    const double e = c.e[m], f = c.f[m];
+    const double e = c.e[mb], f = c.f[mb];
     const double vcr = e * cr - f * ci;               // Re(V_m c_m)
     const double vci = e * ci + f * cr;               // Im(V_m c_m)
-    c.aux[m] = vcr / c.vm[m];
+    c.aux[mb] = vcr / c.vm[mb];
     if (a >= 0 && g) {
       const double r0 = g[2 * a] - vci;
-      const double r1 = s.bus_type[m] == 0 ? g[2 * a + 1] + vcr / c.vm[m] : 0.0;
+      const double r1 = m.bus_type[mb] == 0 ? g[2 * a + 1] + vcr / c.vm[mb] : 0.0;
       c.rr[2 * a] = r0;
       c.rr[2 * a + 1] = r1;
       if (to_y) { c.y[2 * a] = T(r0); c.y[2 * a + 1] = T(r1); }
@@ -455,246 +506,295 @@ __device__ void phase_adj_residual(const DevSym& s, Ctx<T>& c, int tid, int nt,
   __syncthreads();
 }
 
-template <typename T>
-__device__ void phase_set_state(const DevSym& s, Ctx<T>& c, int tid, int nt) {
-  for (int i = tid; i < s.n_bus; i += nt) {
+// e + jf from (|V|, theta) for the scenarios in `mask`
+template <typename T, int S>
+__device__ void phase_set_state(const Dims& D, St<T>& c, int tid, int nt, int mask) {
+  for (int idx = tid; idx < D.n_bus * S; idx += nt) {
+    if (!((mask >> (idx % S)) & 1)) continue;
     double sn, cs;
-    sincos(c.va[i], &sn, &cs);
-    c.e[i] = c.vm[i] * cs;
-    c.f[i] = c.vm[i] * sn;
+    sincos(c.va[idx], &sn, &cs);
+    c.e[idx] = c.vm[idx] * cs;
+    c.f[idx] = c.vm[idx] * sn;
   }
   __syncthreads();
 }
 
 // ----------------------------------------------------------------------------
-// the Newton kernel: one workgroup = one scenario
+// the Newton kernel: one workgroup = one slice of S scenarios
 
-template <typename T, bool LDS>
+template <typename T, bool RES, int S>
 __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const DevSym& s = kp.s;
-  const int b = blockIdx.x;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const StateLayout& L = kp.lay;
+  const int slice = blockIdx.x;
+  const Dims& D = kp.dims;
+  unsigned char* scr = smem;
+  int* piv = reinterpret_cast<int*>(scr + kPivOff);
 
-  double* gd = kp.ws_d + (size_t)b * L.sd;
-  T* gt = reinterpret_cast<T*>(kp.ws_t) + (size_t)b * L.st;
-  int* gi = kp.ws_i + (size_t)b * 4;
-
-  Ctx<T> c;
-  c.red = reinterpret_cast<double*>(smem);
-  c.flags = reinterpret_cast<int*>(smem + kRedBytes);
-  unsigned char* dyn = smem + kScratchBytes;
-  if (LDS) {
-    bind_state<T>(c, reinterpret_cast<double*>(dyn),
-                  reinterpret_cast<T*>(dyn + 8 * (size_t)L.sd), L);
-    c.wsp = nullptr;
-  } else {
-    bind_state<T>(c, gd, gt, L);
-    c.wsp = reinterpret_cast<T*>(dyn);
+  const unsigned char* mbase = kp.sym;
+  if (RES) {   // the shared symbolic image, once per workgroup, 16 bytes per lane
+    int4* dst = reinterpret_cast<int4*>(smem + kScratchBytes);
+    const int4* src = reinterpret_cast<const int4*>(kp.sym);
+    for (int q = tid; q < (kp.so.newton_bytes >> 4); q += nt) dst[q] = src[q];
+    mbase = smem + kScratchBytes;
   }
-  int* zflag = c.flags + kZeroPivotFlag;
-  if (tid == 0) *zflag = 0;
+  const Sym m = bind_sym(mbase, kp.sym, kp.so);
+  St<T> c;
+  T* wsp = nullptr;
+  if (RES) {
+    double* d = reinterpret_cast<double*>(smem + kScratchBytes + kp.so.newton_bytes);
+    c = bind_state<T, S>(d, reinterpret_cast<T*>(d + (size_t)kp.llay.sd * S), kp.llay);
+  } else {
+    c = bind_state<T, 1>(kp.ws_d + (size_t)slice * kp.lay.sd,
+                         reinterpret_cast<T*>(kp.ws_t) + (size_t)slice * kp.lay.st, kp.lay);
+    wsp = reinterpret_cast<T*>(smem + kScratchBytes);
+  }
+  if (tid < S) piv[tid] = 0;
 
-  const int n = s.n_bus;
-  const size_t io = (size_t)b * n;
-  // inputs: specified injections and the start point
-  for (int i = tid; i < n; i += nt) {
-    const int bt = s.bus_type[i];
-    const double pg = (kp.pg && bt == 1) ? kp.pg[io + i] : 0.0;
-    c.ps[i] = pg - kp.pd[io + i];
-    c.qs[i] = -kp.qd[io + i];
-    if (kp.mode == MODE_SOLVE) {
-      c.vm[i] = bt == 0 ? 1.0 : kp.vset[io + i];
-      c.va[i] = 0.0;
+  const int n = D.n_bus, nb = D.nb;
+  int act = 0;   // scenarios of the slice still iterating (identical in every thread)
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+    if (slice * S + s < kp.count) act |= 1 << s;
+  const int valid = act;
+
+  // inputs: specified injections and the start point; padding scenarios of
+  // the last slice get an empty problem and are never written back
+  for (int idx = tid; idx < n * S; idx += nt) {
+    const int i = idx / S, s = idx % S;
+    const int b = slice * S + s;
+    const int bt = m.bus_type[i];
+    if (b < kp.count) {
+      const size_t o = (size_t)b * n + i;
+      const double pg = (kp.pg && bt == 1) ? kp.pg[o] : 0.0;
+      c.ps[idx] = pg - kp.pd[o];
+      c.qs[idx] = -kp.qd[o];
+      if (kp.mode == MODE_SOLVE) {
+        c.vm[idx] = bt == 0 ? 1.0 : kp.vset[o];
+        c.va[idx] = 0.0;
+      } else {
+        c.vm[idx] = kp.vm_in[o];
+        c.va[idx] = bt == 2 ? 0.0 : kp.va_in[o];
+      }
     } else {
-      c.vm[i] = kp.vm_in[io + i];
-      c.va[i] = bt == 2 ? 0.0 : kp.va_in[io + i];
+      c.ps[idx] = 0.0;
+      c.qs[idx] = 0.0;
+      c.vm[idx] = 1.0;
+      c.va[idx] = 0.0;
     }
   }
   __syncthreads();
-  phase_set_state(s, c, tid, nt);
+  phase_set_state<T, S>(D, c, tid, nt, (1 << S) - 1);
 
-  const int nb = s.nb;
-  int t = 0, status = -1;
-  double fn = 0.0;
+  int iters[S], status[S];
+  double fnv[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) { iters[s] = 0; status[s] = 0; fnv[s] = 0.0; }
   const bool mixed = sizeof(T) == 4;
+  const int gmin = RES ? (kp.gmin > S ? kp.gmin : S) : kp.gmin;
   while (true) {
-    int bad = 0;
-    fn = phase_mismatch(s, c, tid, nt, &bad);
-    if (kp.mode == MODE_EVAL_MISMATCH) { status = 0; break; }
-    if (bad) { status = 2; break; }
-    if (kp.mode == MODE_SOLVE) {
-      if (fn < kp.tol) { status = 0; break; }
-      if (t >= kp.max_iter) { status = 1; break; }
+    double fn[S];
+    int bad[S];
+    phase_mismatch<T, S>(m, D, c, tid, nt, fn, bad, scr);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (!((act >> s) & 1)) continue;
+      fnv[s] = fn[s];
+      if (bad[s]) { status[s] = 2; act &= ~(1 << s); continue; }
+      if (kp.mode == MODE_SOLVE) {
+        if (fn[s] < kp.tol) { status[s] = 0; act &= ~(1 << s); }
+        else if (iters[s] >= kp.max_iter) { status[s] = 1; act &= ~(1 << s); }
+      }
     }
-    if (kp.mode == MODE_EVAL_FACTOR) {
-      status = 0;
-      break;
-    }
-    for (int q = tid; q < 2 * nb; q += nt) c.y[q] = T(-c.F[q]);
+    if (kp.mode == MODE_EVAL_MISMATCH || kp.mode == MODE_EVAL_FACTOR) break;
+    if (!act) break;
+    for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
     __syncthreads();
-    phase_factor<T, LDS>(s, c, tid, nt, kp.gmin, kp.wstride, true, true);
-    if (*zflag) { status = 3; break; }
-    phase_bsolve(s, c, tid, nt, kp.gmin);
-    for (int q = tid; q < 2 * nb; q += nt) c.dx[q] = double(c.y[q]);
+    phase_factor<T, S, RES>(m, D, c, wsp, tid, nt, gmin, kp.wstride, true, true, piv);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      if (((act >> s) & 1) && piv[s]) { status[s] = 3; act &= ~(1 << s); }
+    if (!act) break;
+    phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
+    for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
     __syncthreads();
     if (mixed) {
       for (int r = 0; r < kp.refine; ++r) {
-        phase_dv(s, c, tid, nt);
-        phase_residual(s, c, tid, nt);
-        phase_fsolve(s, c, tid, nt, kp.gmin);
-        phase_bsolve(s, c, tid, nt, kp.gmin);
-        for (int q = tid; q < 2 * nb; q += nt) c.dx[q] += double(c.y[q]);
+        phase_dv<T, S>(m, D, c, tid, nt);
+        phase_residual<T, S>(m, D, c, tid, nt);
+        phase_fsolve<T, S>(m, D, c, tid, nt, gmin);
+        phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
+        for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] += double(c.y[q]);
         __syncthreads();
       }
     }
-    if (kp.mode == MODE_EVAL_STEP) { status = 0; break; }
-    // state update: theta on non-slack buses, |V| on PQ buses
-    for (int i = tid; i < n; i += nt) {
-      const int a = s.bus_blk[i];
-      if (a >= 0) {
-        c.va[i] += c.dx[2 * a];
-        if (s.bus_type[i] == 0) c.vm[i] += c.dx[2 * a + 1];
+    if (kp.mode == MODE_EVAL_STEP) break;
+    // state update of the active scenarios: theta on non-slack buses, |V| on PQ buses
+    for (int idx = tid; idx < n * S; idx += nt) {
+      const int i = idx / S, s = idx % S;
+      const int a = m.bus_blk[i];
+      if (a >= 0 && ((act >> s) & 1)) {
+        c.va[idx] += c.dx[sP<S>(a, s)];
+        if (m.bus_type[i] == 0) c.vm[idx] += c.dx[sP<S>(a, s) + 1];
       }
     }
     __syncthreads();
-    phase_set_state(s, c, tid, nt);
-    ++t;
+    phase_set_state<T, S>(D, c, tid, nt, act);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      if ((act >> s) & 1) iters[s]++;
   }
 
   // outputs
   if (kp.mode == MODE_SOLVE) {
-    for (int i = tid; i < n; i += nt) {
-      kp.vm_out[io + i] = c.vm[i];
-      kp.va_out[io + i] = c.va[i];
+    for (int idx = tid; idx < n * S; idx += nt) {
+      const int i = idx / S, s = idx % S;
+      const int b = slice * S + s;
+      if (b < kp.count) {
+        kp.vm_out[(size_t)b * n + i] = c.vm[idx];
+        kp.va_out[(size_t)b * n + i] = c.va[idx];
+      }
     }
-    if (tid == 0) {
-      if (kp.iters_out) kp.iters_out[b] = t;
-      if (kp.status_out) kp.status_out[b] = status;
-      if (kp.fnorm_out) kp.fnorm_out[b] = status == 2 ? __builtin_nan("") : fn;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int b = slice * S + s;
+      if (tid == s && b < kp.count) {
+        if (kp.iters_out) kp.iters_out[b] = iters[s];
+        if (kp.status_out) kp.status_out[b] = status[s];
+        if (kp.fnorm_out) kp.fnorm_out[b] = status[s] == 2 ? __builtin_nan("") : fnv[s];
+      }
     }
   } else if (kp.mode == MODE_EVAL_MISMATCH || kp.mode == MODE_EVAL_STEP) {
-    if (b < kp.count) {
-      const double* src = kp.mode == MODE_EVAL_MISMATCH ? c.F : c.dx;
-      const int nj = s.nj;
+    const int nj = D.nj;
+    for (int idx = tid; idx < n * S; idx += nt) {
+      const int i = idx / S, s = idx % S;
+      const int b = slice * S + s;
+      const int a = m.bus_blk[i];
+      if (b >= kp.count || a < 0) continue;
       double* o = kp.out + (size_t)b * nj;
-      for (int i = tid; i < n; i += nt) {
-        const int a = s.bus_blk[i];
-        if (a < 0) continue;
-        if (kp.mode == MODE_EVAL_MISMATCH) {
-          o[s.ord_p[i]] = src[2 * a];
-          if (s.bus_type[i] == 0) o[s.npvpq + s.ord_q[i]] = src[2 * a + 1];
-        } else {
-          o[s.npq + s.ord_p[i]] = src[2 * a];
-          if (s.bus_type[i] == 0) o[s.ord_q[i]] = src[2 * a + 1];
-        }
+      if (kp.mode == MODE_EVAL_MISMATCH) {
+        o[m.ord_p[i]] = c.F[sP<S>(a, s)];
+        if (m.bus_type[i] == 0) o[D.npvpq + m.ord_q[i]] = c.F[sP<S>(a, s) + 1];
+      } else {
+        o[D.npq + m.ord_p[i]] = c.dx[sP<S>(a, s)];
+        if (m.bus_type[i] == 0) o[m.ord_q[i]] = c.dx[sP<S>(a, s) + 1];
       }
     }
   }
   // keep the converged state and the factors of J1 at it for the adjoint
   const bool keep = (kp.mode == MODE_SOLVE && kp.keep) || kp.mode == MODE_EVAL_FACTOR;
-  if (keep && status == 0) {
-    phase_factor<T, LDS>(s, c, tid, nt, kp.gmin, kp.wstride, true, false);
-    if (*zflag) status = 3;
-    if (LDS) {
-      T* glu = gt + L.o_lu;
-      for (int q = tid; q < 4 * s.nnzb; q += nt) glu[q] = c.lu[q];
-      for (int q = tid; q < 4 * nb; q += nt) gt[L.o_dinv + q] = c.dinv[q];
-      for (int i = tid; i < n; i += nt) {
-        gd[L.o_e + i] = c.e[i]; gd[L.o_f + i] = c.f[i];
-        gd[L.o_vm + i] = c.vm[i]; gd[L.o_va + i] = c.va[i];
+  if (keep) {
+    if (tid < S) piv[tid] = 0;
+    __syncthreads();
+    phase_factor<T, S, RES>(m, D, c, wsp, tid, nt, gmin, kp.wstride, true, false, piv);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      if (status[s] == 0 && piv[s]) status[s] = 3;
+    if (RES) {   // scatter the slice into the per-scenario HBM workspace
+      for (int s = 0; s < S; ++s) {
+        const int b = slice * S + s;
+        if (b >= kp.count) break;
+        double* gd = kp.ws_d + (size_t)b * kp.lay.sd;
+        T* gt = reinterpret_cast<T*>(kp.ws_t) + (size_t)b * kp.lay.st;
+        for (int q = tid; q < 4 * D.nnzb; q += nt) gt[kp.lay.o_lu + q] = c.lu[sB<S>(q >> 2, s) + (q & 3)];
+        for (int q = tid; q < 4 * nb; q += nt) gt[kp.lay.o_dinv + q] = c.dinv[sB<S>(q >> 2, s) + (q & 3)];
+        for (int i = tid; i < n; i += nt) {
+          gd[kp.lay.o_e + i] = c.e[sI<S>(i, s)];
+          gd[kp.lay.o_f + i] = c.f[sI<S>(i, s)];
+          gd[kp.lay.o_vm + i] = c.vm[sI<S>(i, s)];
+          gd[kp.lay.o_va + i] = c.va[sI<S>(i, s)];
+        }
       }
     }
   }
-  if (tid == 0) { gi[0] = keep ? status : -1; gi[1] = t; }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int b = slice * S + s;
+    if (tid == s && b < kp.count) {
+      int* gi = kp.ws_i + (size_t)b * 4;
+      gi[0] = keep ? status[s] : -1;
+      gi[1] = iters[s];
+    }
+  }
+  (void)valid;
 }
 
 // ----------------------------------------------------------------------------
-// adjoint kernel (HBM-resident state and factors)
+// adjoint kernel (one scenario per workgroup, HBM-resident state and factors)
 
 template <typename T>
 __global__ void __launch_bounds__(1024) k_adjoint(KParams kp) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const DevSym& s = kp.s;
+  const Dims& D = kp.dims;
+  const Sym m = bind_sym(kp.sym, kp.sym, kp.so);
   const int b = blockIdx.x;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const StateLayout& L = kp.lay;
-  double* gd = kp.ws_d + (size_t)b * L.sd;
-  T* gt = reinterpret_cast<T*>(kp.ws_t) + (size_t)b * L.st;
-  const int* gi = kp.ws_i + (size_t)b * 4;
-  Ctx<T> c;
-  c.red = reinterpret_cast<double*>(smem);
-  c.flags = reinterpret_cast<int*>(smem + kRedBytes);
-  bind_state<T>(c, gd, gt, L);
-  c.wsp = nullptr;
-  const int n = s.n_bus, nb = s.nb;
+  St<T> c = bind_state<T, 1>(kp.ws_d + (size_t)b * kp.lay.sd,
+                             reinterpret_cast<T*>(kp.ws_t) + (size_t)b * kp.lay.st, kp.lay);
+  const int n = D.n_bus, nb = D.nb;
   const size_t io = (size_t)b * n;
-  const bool ok = gi[0] == 0;
+  const bool ok = kp.ws_i[(size_t)b * 4] == 0;
   const bool eval = kp.mode == MODE_EVAL_ADJOINT;
 
-  // g_z1 per block: (dL/dtheta, dL/d|V| on PQ) -> kept in F (FP64), y (T)
-  if (eval) {
-    const double* rhs = kp.rhs + (size_t)b * s.nj;
-    for (int i = tid; i < n; i += nt) {
-      const int a = s.bus_blk[i];
-      if (a < 0) continue;
-      const double g0 = rhs[s.npq + s.ord_p[i]];
-      const double g1 = s.bus_type[i] == 0 ? rhs[s.ord_q[i]] : 0.0;
-      c.F[2 * a] = g0; c.F[2 * a + 1] = g1;
+  // g_z1 per block: (dL/dtheta, dL/d|V| on PQ) -> F (FP64)
+  for (int i = tid; i < n; i += nt) {
+    const int a = m.bus_blk[i];
+    if (a < 0) continue;
+    double g0, g1;
+    if (eval) {
+      const double* rhs = kp.rhs + (size_t)b * D.nj;
+      g0 = rhs[D.npq + m.ord_p[i]];
+      g1 = m.bus_type[i] == 0 ? rhs[m.ord_q[i]] : 0.0;
+    } else {
+      g0 = kp.g_va[io + i];
+      g1 = m.bus_type[i] == 0 ? kp.g_vm[io + i] : 0.0;
     }
-  } else {
-    for (int i = tid; i < n; i += nt) {
-      const int a = s.bus_blk[i];
-      if (a < 0) continue;
-      const double g0 = kp.g_va[io + i];
-      const double g1 = s.bus_type[i] == 0 ? kp.g_vm[io + i] : 0.0;
-      c.F[2 * a] = g0; c.F[2 * a + 1] = g1;
-    }
+    c.F[2 * a] = g0;
+    c.F[2 * a + 1] = g1;
   }
   // I at the kept state (needed by the FP64 transposed products)
   for (int i = tid; i < n; i += nt) {
     double ir = 0.0, ii = 0.0;
-    for (int q = s.y_rp[i]; q < s.y_rp[i + 1]; ++q) {
-      const int j = s.y_ci[q];
-      ir += s.y_g[q] * c.e[j] - s.y_b[q] * c.f[j];
-      ii += s.y_g[q] * c.f[j] + s.y_b[q] * c.e[j];
+    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
+      const int j = m.y_ci[q];
+      ir += m.y_g[q] * c.e[j] - m.y_b[q] * c.f[j];
+      ii += m.y_g[q] * c.f[j] + m.y_b[q] * c.e[j];
     }
-    c.ire[i] = ir; c.iim[i] = ii;
+    c.ire[i] = ir;
+    c.iim[i] = ii;
   }
   __syncthreads();
   for (int q = tid; q < 2 * nb; q += nt) c.y[q] = T(c.F[q]);
   __syncthreads();
-  phase_ut_solve(s, c, tid, nt, kp.gmin);
-  phase_lt_solve(s, c, tid, nt, kp.gmin);
+  phase_ut_solve<T>(m, D, c, tid, nt, 1);
+  phase_lt_solve<T>(m, D, c, tid, nt, 1);
   for (int q = tid; q < 2 * nb; q += nt) c.dx[q] = double(c.y[q]);
   __syncthreads();
   if (sizeof(T) == 4) {
     for (int r = 0; r < kp.refine; ++r) {
-      phase_adj_residual(s, c, tid, nt, c.dx, c.F, true);
-      phase_ut_solve(s, c, tid, nt, kp.gmin);
-      phase_lt_solve(s, c, tid, nt, kp.gmin);
+      phase_adj_residual<T>(m, D, c, tid, nt, c.dx, c.F, true);
+      phase_ut_solve<T>(m, D, c, tid, nt, 1);
+      phase_lt_solve<T>(m, D, c, tid, nt, 1);
       for (int q = tid; q < 2 * nb; q += nt) c.dx[q] += double(c.y[q]);
       __syncthreads();
     }
   }
   if (eval) {
     if (b < kp.count) {
-      double* o = kp.out + (size_t)b * s.nj;
+      double* o = kp.out + (size_t)b * D.nj;
       for (int i = tid; i < n; i += nt) {
-        const int a = s.bus_blk[i];
+        const int a = m.bus_blk[i];
         if (a < 0) continue;
-        o[s.ord_p[i]] = c.dx[2 * a];
-        if (s.bus_type[i] == 0) o[s.npvpq + s.ord_q[i]] = c.dx[2 * a + 1];
+        o[m.ord_p[i]] = c.dx[2 * a];
+        if (m.bus_type[i] == 0) o[D.npvpq + m.ord_q[i]] = c.dx[2 * a + 1];
       }
     }
     return;
   }
   // J3^T lam via the transposed product at the solution (-(J3^T lam) lands in aux)
-  phase_adj_residual(s, c, tid, nt, c.dx, nullptr, false);
+  phase_adj_residual<T>(m, D, c, tid, nt, c.dx, nullptr, false);
   for (int i = tid; i < n; i += nt) {
-    const int a = s.bus_blk[i];
-    const int bt = s.bus_type[i];
+    const int a = m.bus_blk[i];
+    const int bt = m.bus_type[i];
     double gpd = 0.0, gqd = 0.0, gpg = 0.0, gvs = 0.0;
     if (ok) {
       if (a >= 0) {
@@ -715,44 +815,47 @@ __global__ void __launch_bounds__(1024) k_adjoint(KParams kp) {
 // dense J1 export in the paper's ordering (evaluation entry point)
 
 __global__ void __launch_bounds__(256) k_jacobian_dense(KParams kp) {
-  const DevSym& s = kp.s;
+  const Dims& D = kp.dims;
+  const Sym m = bind_sym(kp.sym, kp.sym, kp.so);
   const int b = blockIdx.x;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int n = s.n_bus, nj = s.nj;
+  const int n = D.n_bus, nj = D.nj;
   const size_t io = (size_t)b * n;
   double* gd = kp.ws_d + (size_t)b * kp.lay.sd;
   double *e = gd + kp.lay.o_e, *f = gd + kp.lay.o_f, *vm = gd + kp.lay.o_vm;
   double *ire = gd + kp.lay.o_ire, *iim = gd + kp.lay.o_iim;
   for (int i = tid; i < n; i += nt) {
     vm[i] = kp.vm_in[io + i];
-    const double va = s.bus_type[i] == 2 ? 0.0 : kp.va_in[io + i];
+    const double va = m.bus_type[i] == 2 ? 0.0 : kp.va_in[io + i];
     e[i] = vm[i] * cos(va);
     f[i] = vm[i] * sin(va);
   }
   __syncthreads();
   for (int i = tid; i < n; i += nt) {
     double ir = 0.0, ii = 0.0;
-    for (int q = s.y_rp[i]; q < s.y_rp[i + 1]; ++q) {
-      const int j = s.y_ci[q];
-      ir += s.y_g[q] * e[j] - s.y_b[q] * f[j];
-      ii += s.y_g[q] * f[j] + s.y_b[q] * e[j];
+    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
+      const int j = m.y_ci[q];
+      ir += m.y_g[q] * e[j] - m.y_b[q] * f[j];
+      ii += m.y_g[q] * f[j] + m.y_b[q] * e[j];
     }
-    ire[i] = ir; iim[i] = ii;
+    ire[i] = ir;
+    iim[i] = ii;
   }
   __syncthreads();
   double* o = kp.out + (size_t)b * nj * nj;
   for (size_t q = tid; q < (size_t)nj * nj; q += nt) o[q] = 0.0;
   __syncthreads();
   for (int i = tid; i < n; i += nt) {
-    if (s.bus_type[i] == 2) continue;
-    const int rP = s.ord_p[i];
-    const int rQ = s.bus_type[i] == 0 ? s.npvpq + s.ord_q[i] : -1;
-    for (int q = s.y_rp[i]; q < s.y_rp[i + 1]; ++q) {
-      const int m = s.y_ci[q];
-      if (s.bus_type[m] == 2) continue;
-      const B4d x = jac_entries(i, m, s.y_g[q], s.y_b[q], e, f, vm, ire, iim);
-      const int cT = s.npq + s.ord_p[m];
-      const int cV = s.bus_type[m] == 0 ? s.ord_q[m] : -1;
+    if (m.bus_type[i] == 2) continue;
+    const int rP = m.ord_p[i];
+    const int rQ = m.bus_type[i] == 0 ? D.npvpq + m.ord_q[i] : -1;
+    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
+      const int j = m.y_ci[q];
+      if (m.bus_type[j] == 2) continue;
+      const J4 x = (i == j) ? jac_diag(m.y_g[q], m.y_b[q], e[i], f[i], vm[i], ire[i], iim[i])
+                            : jac_off(m.y_g[q], m.y_b[q], e[i], f[i], e[j], f[j], vm[j]);
+      const int cT = D.npq + m.ord_p[j];
+      const int cV = m.bus_type[j] == 0 ? m.ord_q[j] : -1;
       o[(size_t)rP * nj + cT] = x.v[0];
       if (cV >= 0) o[(size_t)rP * nj + cV] = x.v[1];
       if (rQ >= 0) {
@@ -767,28 +870,34 @@ __global__ void __launch_bounds__(256) k_jacobian_dense(KParams kp) {
 // launchers
 
 template <typename T>
-static hipError_t launch_newton_t(const KParams& kp, int grid, int nt, size_t lds, bool lds_res,
-                                  hipStream_t st) {
-  if (lds_res) {
-    hipLaunchKernelGGL((k_newton<T, true>), dim3(grid), dim3(nt), lds, st, kp);
+static hipError_t launch_newton_t(const KParams& kp, int slice, int grid, int nt, size_t lds,
+                                  bool res, hipStream_t st) {
+  dim3 g(grid), b(nt);
+  if (!res) {
+    hipLaunchKernelGGL((k_newton<T, false, 1>), g, b, lds, st, kp);
   } else {
-    hipLaunchKernelGGL((k_newton<T, false>), dim3(grid), dim3(nt), lds, st, kp);
+    switch (slice) {
+      case 1: hipLaunchKernelGGL((k_newton<T, true, 1>), g, b, lds, st, kp); break;
+      case 2: hipLaunchKernelGGL((k_newton<T, true, 2>), g, b, lds, st, kp); break;
+      case 4: hipLaunchKernelGGL((k_newton<T, true, 4>), g, b, lds, st, kp); break;
+      case 8: hipLaunchKernelGGL((k_newton<T, true, 8>), g, b, lds, st, kp); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_newton(const KParams& kp, bool fp32, int grid, int nt, size_t lds, bool lds_res,
-                         hipStream_t st) {
-  return fp32 ? launch_newton_t<float>(kp, grid, nt, lds, lds_res, st)
-              : launch_newton_t<double>(kp, grid, nt, lds, lds_res, st);
+hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds,
+                         bool lds_res, hipStream_t st) {
+  return fp32 ? launch_newton_t<float>(kp, slice, grid, nt, lds, lds_res, st)
+              : launch_newton_t<double>(kp, slice, grid, nt, lds, lds_res, st);
 }
 
 hipError_t launch_adjoint(const KParams& kp, bool fp32, int grid, int nt, hipStream_t st) {
-  const size_t lds = kScratchBytes;
   if (fp32) {
-    hipLaunchKernelGGL((k_adjoint<float>), dim3(grid), dim3(nt), lds, st, kp);
+    hipLaunchKernelGGL((k_adjoint<float>), dim3(grid), dim3(nt), 0, st, kp);
   } else {
-    hipLaunchKernelGGL((k_adjoint<double>), dim3(grid), dim3(nt), lds, st, kp);
+    hipLaunchKernelGGL((k_adjoint<double>), dim3(grid), dim3(nt), 0, st, kp);
   }
   return hipGetLastError();
 }
@@ -798,17 +907,25 @@ hipError_t launch_jacobian_dense(const KParams& kp, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t set_lds_limits(size_t max_lds) {
+template <typename T>
+static hipError_t set_lds_t(int max_lds) {
   hipError_t e = hipSuccess;
   auto set = [&](const void* fn) {
-    hipError_t r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+    hipError_t r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     if (r != hipSuccess) e = r;
   };
-  set(reinterpret_cast<const void*>(&k_newton<double, true>));
-  set(reinterpret_cast<const void*>(&k_newton<double, false>));
-  set(reinterpret_cast<const void*>(&k_newton<float, true>));
-  set(reinterpret_cast<const void*>(&k_newton<float, false>));
+  set(reinterpret_cast<const void*>(&k_newton<T, false, 1>));
+  set(reinterpret_cast<const void*>(&k_newton<T, true, 1>));
+  set(reinterpret_cast<const void*>(&k_newton<T, true, 2>));
+  set(reinterpret_cast<const void*>(&k_newton<T, true, 4>));
+  set(reinterpret_cast<const void*>(&k_newton<T, true, 8>));
   return e;
+}
+
+hipError_t set_lds_limits(size_t max_lds) {
+  hipError_t e1 = set_lds_t<double>((int)max_lds);
+  hipError_t e2 = set_lds_t<float>((int)max_lds);
+  return e1 != hipSuccess ? e1 : e2;
 }
 
 }  // namespace sable
