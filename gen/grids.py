@@ -66,7 +66,7 @@ SPECS = {
     "c1": GridSpec("c1", 1, 118, 53, 177, 1024, 0.10, 1e-8, load_factor=0.9 ** 7),
     "c2": GridSpec("c2", 2, 1354, 260, 1896, 4096, 0.15, 1e-8, load_factor=0.9 ** 26),
     "c3": GridSpec("c3", 3, 300, 69, 420, 2048, 0.10, 1e-10, load_factor=0.9 ** 17),
-    "c4": GridSpec("c4", 4, 9241, 1400, 12013, 256, 0.10, 1e-8, load_factor=1.0,
+    "c4": GridSpec("c4", 4, 9241, 1400, 12013, 256, 0.10, 1e-8, load_factor=0.9 ** 34,
                    z_scale=(118 / 9241) ** 0.5),
 }
 

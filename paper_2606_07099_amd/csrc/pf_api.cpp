@@ -268,14 +268,16 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   Packer pk;
   sable::SymOffsets& so = t->so;
   so.bus_type = (int)pk.add(S.bus_type); so.bus_blk = (int)pk.add(S.bus_blk);
-  so.blk_bus = (int)pk.add(S.blk_bus); so.y_rp = (int)pk.add(S.y_rp); so.y_ci = (int)pk.add(S.y_ci);
+  so.y_rp = (int)pk.add(S.y_rp); so.y_ci = (int)pk.add(S.y_ci);
   so.y_g = (int)pk.add(S.y_g); so.y_b = (int)pk.add(S.y_b);
   so.rp = (int)pk.add(S.rp); so.ci = (int)pk.add(S.ci); so.diag = (int)pk.add(S.diag);
-  so.lu_src = (int)pk.add(S.lu_src); so.upd_start = (int)pk.add(S.upd_start);
-  so.upd_tgt = (int)pk.add(S.upd_tgt);
+  so.fill4 = (int)pk.add(S.fill4); so.task_ptr = (int)pk.add(S.task_ptr);
+  so.task4 = (int)pk.add(S.task4); so.step4 = (int)pk.add(S.step4);
+  so.step_ts = (int)pk.add(S.step_ts); so.upd_tgt = (int)pk.add(S.upd_tgt);
   so.lev_l_ptr = (int)pk.add(S.lev_l_ptr); so.lev_l_rows = (int)pk.add(S.lev_l_rows);
   so.lev_u_ptr = (int)pk.add(S.lev_u_ptr); so.lev_u_rows = (int)pk.add(S.lev_u_rows);
   so.newton_bytes = (int)pk.align();
+  so.blk_bus = (int)pk.add(S.blk_bus); so.lu_src = (int)pk.add(S.lu_src);
   so.mirror = (int)pk.add(S.mirror); so.y_tr = (int)pk.add(S.y_tr);
   so.ord_p = (int)pk.add(ord_p); so.ord_q = (int)pk.add(ord_q);
   so.total_bytes = (int)pk.align();

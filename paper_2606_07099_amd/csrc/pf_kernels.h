@@ -30,11 +30,11 @@ constexpr int kScratchBytes = 2048;
 // memory; the prefix [0, newton_bytes) is what the Newton kernel reads and is
 // copied whole into LDS when the slice of a workgroup is LDS-resident).
 struct SymOffsets {
-  int bus_type, bus_blk, blk_bus, y_rp, y_ci, y_g, y_b;
-  int rp, ci, diag, lu_src, upd_start, upd_tgt;
+  int bus_type, bus_blk, y_rp, y_ci, y_g, y_b;
+  int rp, ci, diag, fill4, task_ptr, task4, step4, step_ts, upd_tgt;
   int lev_l_ptr, lev_l_rows, lev_u_ptr, lev_u_rows;
   int newton_bytes;
-  int mirror, y_tr, ord_p, ord_q;
+  int blk_bus, lu_src, mirror, y_tr, ord_p, ord_q;
   int total_bytes;
 };
 

@@ -3,10 +3,11 @@
 // One workgroup owns a slice of S scenarios (S = 1, 2, 4 or 8) for the whole
 // Newton solve, with no host round trip per iteration: complex Y_bus SpMV +
 // mismatch, per-scenario convergence test, Jacobian value evaluation
-// (Algorithm 1) fused into a row-oriented 2x2-block LU refactorisation on the
-// fixed symbolic pattern (forward solve fused), the level-scheduled backward
-// solve, FP64-residual refinement in the mixed-precision mode, and the state
-// update.  Converged scenarios of a slice freeze while the others continue.
+// (Algorithm 1) into the fixed symbolic pattern, a 2x2-block LU
+// refactorisation scheduled right-looking by levels (forward solve fused),
+// the level-scheduled backward solve, FP64-residual refinement in the
+// mixed-precision mode, and the state update.  Converged scenarios of a slice
+// freeze while the others continue.
 //
 // Two residency modes:
 //  * LDS-resident (small grids): the symbolic image and the whole state of
@@ -45,11 +46,13 @@ template <int S> __device__ __forceinline__ int sB(int p, int s) { return (p * S
 
 // symbolic arrays, bound to LDS or to the device image
 struct Sym {
-  const int *bus_type, *bus_blk, *blk_bus, *y_rp, *y_ci;
+  const int *bus_type, *bus_blk, *y_rp, *y_ci;
   const double *y_g, *y_b;
-  const int *rp, *ci, *diag, *lu_src, *upd_start, *upd_tgt;
+  const int *rp, *ci, *diag;
+  const int4 *fill4, *task4, *step4;
+  const int *task_ptr, *step_ts, *upd_tgt;
   const int *lev_l_ptr, *lev_l_rows, *lev_u_ptr, *lev_u_rows;
-  const int *mirror, *y_tr, *ord_p, *ord_q;
+  const int *blk_bus, *lu_src, *mirror, *y_tr, *ord_p, *ord_q;
 };
 
 __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned char* g,
@@ -57,7 +60,6 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
   Sym m;
   m.bus_type = reinterpret_cast<const int*>(nb + o.bus_type);
   m.bus_blk = reinterpret_cast<const int*>(nb + o.bus_blk);
-  m.blk_bus = reinterpret_cast<const int*>(nb + o.blk_bus);
   m.y_rp = reinterpret_cast<const int*>(nb + o.y_rp);
   m.y_ci = reinterpret_cast<const int*>(nb + o.y_ci);
   m.y_g = reinterpret_cast<const double*>(nb + o.y_g);
@@ -65,13 +67,18 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
   m.rp = reinterpret_cast<const int*>(nb + o.rp);
   m.ci = reinterpret_cast<const int*>(nb + o.ci);
   m.diag = reinterpret_cast<const int*>(nb + o.diag);
-  m.lu_src = reinterpret_cast<const int*>(nb + o.lu_src);
-  m.upd_start = reinterpret_cast<const int*>(nb + o.upd_start);
+  m.fill4 = reinterpret_cast<const int4*>(nb + o.fill4);
+  m.task_ptr = reinterpret_cast<const int*>(nb + o.task_ptr);
+  m.task4 = reinterpret_cast<const int4*>(nb + o.task4);
+  m.step4 = reinterpret_cast<const int4*>(nb + o.step4);
+  m.step_ts = reinterpret_cast<const int*>(nb + o.step_ts);
   m.upd_tgt = reinterpret_cast<const int*>(nb + o.upd_tgt);
   m.lev_l_ptr = reinterpret_cast<const int*>(nb + o.lev_l_ptr);
   m.lev_l_rows = reinterpret_cast<const int*>(nb + o.lev_l_rows);
   m.lev_u_ptr = reinterpret_cast<const int*>(nb + o.lev_u_ptr);
   m.lev_u_rows = reinterpret_cast<const int*>(nb + o.lev_u_rows);
+  m.blk_bus = reinterpret_cast<const int*>(g + o.blk_bus);
+  m.lu_src = reinterpret_cast<const int*>(g + o.lu_src);
   m.mirror = reinterpret_cast<const int*>(g + o.mirror);
   m.y_tr = reinterpret_cast<const int*>(g + o.y_tr);
   m.ord_p = reinterpret_cast<const int*>(g + o.ord_p);
@@ -121,25 +128,22 @@ __device__ __forceinline__ J4 jac_off(double G, double B, double ei, double fi, 
   return {{-gs_bc, -gc_bs / vmm, gc_bs, -gs_bc / vmm}};
 }
 
-// The 2x2 block of the padded block system at LU position p of block row a
-// for scenario s.  PV buses keep a dummy |V| unknown and a dummy dQ row:
-// identity on the diagonal, zero coupling; fill-in positions start at zero.
+// The 2x2 block of the padded block system at LU position p for scenario s.
+// PV buses keep a dummy |V| unknown and a dummy dQ row: identity on the
+// diagonal, zero coupling; fill-in positions start at zero.
 template <typename T, int S>
-__device__ __forceinline__ Blk<T> fill_block(const Sym& m, const St<T>& c, int a, int p, int s) {
-  const int src = m.lu_src[p];
-  const int j = m.ci[p];
-  const bool dg = (j == a);
-  if (src < 0 && !dg) return {T(0), T(0), T(0), T(0)};
-  const int i = m.blk_bus[a], mm = m.blk_bus[j];
-  const double G = src < 0 ? 0.0 : m.y_g[src];
-  const double Bv = src < 0 ? 0.0 : m.y_b[src];
-  const int is = sI<S>(i, s);
+__device__ __forceinline__ Blk<T> fill_block(const Sym& m, const St<T>& c, int p, int s) {
+  const int4 r = m.fill4[p];   // Y entry, row bus, column bus, flags
+  const bool dg = r.w & 1;
+  if (r.x < 0 && !dg) return {T(0), T(0), T(0), T(0)};
+  const double G = r.x < 0 ? 0.0 : m.y_g[r.x];
+  const double Bv = r.x < 0 ? 0.0 : m.y_b[r.x];
+  const int is = sI<S>(r.y, s), ms = sI<S>(r.z, s);
   J4 x = dg ? jac_diag(G, Bv, c.e[is], c.f[is], c.vm[is], c.ire[is], c.iim[is])
-            : jac_off(G, Bv, c.e[is], c.f[is], c.e[sI<S>(mm, s)], c.f[sI<S>(mm, s)], c.vm[sI<S>(mm, s)]);
-  const bool pv_i = m.bus_type[i] == 1, pv_m = m.bus_type[mm] == 1;
-  if (pv_i) { x.v[2] = 0.0; x.v[3] = 0.0; }
-  if (pv_m) { x.v[1] = 0.0; x.v[3] = 0.0; }
-  if (dg && pv_i) x.v[3] = 1.0;
+            : jac_off(G, Bv, c.e[is], c.f[is], c.e[ms], c.f[ms], c.vm[ms]);
+  if (r.w & 2) { x.v[2] = 0.0; x.v[3] = 0.0; }
+  if (r.w & 4) { x.v[1] = 0.0; x.v[3] = 0.0; }
+  if ((r.w & 3) == 3) x.v[3] = 1.0;
   return {T(x.v[0]), T(x.v[1]), T(x.v[2]), T(x.v[3])};
 }
 
@@ -149,6 +153,16 @@ __device__ __forceinline__ int pick_group(int nrows, int nt, int gmin) {
   int g = 64;
   while (g > gmin && (nt / g) < nrows) g >>= 1;
   return g;
+}
+
+// group geometry for G lanes per item (G a power of two)
+struct Grp {
+  int G, gid, lane, ng;
+};
+__device__ __forceinline__ Grp groups(int nitems, int tid, int nt, int gmin) {
+  const int G = pick_group(nitems, nt, gmin);
+  const int lg = __builtin_ctz(G);
+  return {G, tid >> lg, tid & (G - 1), nt >> lg};
 }
 
 // sum over the G/S entry lanes of one scenario inside a group
@@ -221,78 +235,89 @@ __device__ void phase_mismatch(const Sym& m, const Dims& D, St<T>& c, int tid, i
   block_max<S>(mx, bad, fn, bd, scr, tid, nt);
 }
 
-// Row-oriented block LU of one row (Doolittle by rows) for the S scenarios
-// of the slice: fill the row's J1 values, eliminate it against the finished
-// rows k in L(a,:) in increasing order (L_ak = A_ak U_kk^-1; A_aj -= L_ak U_kj
-// for j in U(k,>k)), apply the same L_ak to the right-hand side (forward
-// solve), and invert the pivot block.  The G lanes of a group share the row
-// (lane = scenario + S * entry) and belong to one wavefront, whose LDS
-// operations complete in program order, so a value one lane writes in step k
-// is seen by every lane in step k+1.  W is the row: in place in an
-// LDS-resident slice, a staging copy in LDS otherwise.
-template <typename T, int S, bool RES>
-__device__ void factor_row(const Sym& m, St<T>& c, int a, int l, int G, T* W, bool fill, bool fwd,
-                           int* piv) {
-  const int s = l % S, e = l / S, E = G / S;
-  const int rs = m.rp[a], re = m.rp[a + 1], dg = m.diag[a];
-  const int len = re - rs;
-  if (fill) {
-    for (int q = e; q < len; q += E) st_blk(W + sB<S>(q, s), fill_block<T, S>(m, c, a, rs + q, s));
+// Jacobian values of every block of the pattern (fill-in blocks zeroed) for
+// the S scenarios: independent work, one pass before the factorisation.
+template <typename T, int S>
+__device__ void phase_fill(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+  for (int idx = tid; idx < D.nnzb * S; idx += nt) {
+    const int p = idx / S, s = idx % S;
+    st_blk(c.lu + sB<S>(p, s), fill_block<T, S>(m, c, p, s));
   }
-  T y0 = T(0), y1 = T(0);
-  if (fwd) { y0 = c.y[sP<S>(a, s)]; y1 = c.y[sP<S>(a, s) + 1]; }
-  for (int p = rs; p < dg; ++p) {
-    const int k = m.ci[p];
-    const int q = p - rs;
-    const Blk<T> L = mul(ld_blk(W + sB<S>(q, s)), ld_blk(c.dinv + sB<S>(k, s)));
-    if (fwd) {
-      const T yk0 = c.y[sP<S>(k, s)], yk1 = c.y[sP<S>(k, s) + 1];
-      y0 -= L.a * yk0 + L.b * yk1;
-      y1 -= L.c * yk0 + L.d * yk1;
-    }
-    const int ks = m.diag[k] + 1;
-    const int n = m.rp[k + 1] - ks;
-    const int ts = m.upd_start[p];
-    for (int t = e; t < n; t += E) {
-      const Blk<T> U = ld_blk(c.lu + sB<S>(ks + t, s));
-      T* w = W + sB<S>(m.upd_tgt[ts + t], s);
-      Blk<T> x = ld_blk(w);
-      const Blk<T> LU = mul(L, U);
-      x.a -= LU.a; x.b -= LU.b; x.c -= LU.c; x.d -= LU.d;
-      st_blk(w, x);
-    }
-    if (e == 0) st_blk(W + sB<S>(q, s), L);
-  }
-  if (e == 0) {
-    const Blk<T> Dk = ld_blk(W + sB<S>(dg - rs, s));
-    const T det = Dk.a * Dk.d - Dk.b * Dk.c;
-    const T inv = T(1) / det;
-    const Blk<T> Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
-    // pivots of the block: a, then the Schur complement d - c b / a
-    const T p1 = Dk.a, p2 = det / Dk.a;
-    const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
-    const bool zero = !(fabs(p1) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
-                      !(fabs(p2) > eps * (fabs(Dk.c) + fabs(Dk.d))) || !isfinite(inv);
-    if (zero) piv[s] = 1;
-    st_blk(c.dinv + sB<S>(a, s), Di);
-    if (fwd) { c.y[sP<S>(a, s)] = y0; c.y[sP<S>(a, s) + 1] = y1; }
-  }
-  if (!RES) {
-    for (int q = e; q < len; q += E) st_blk(c.lu + sB<S>(rs + q, s), ld_blk(W + sB<S>(q, s)));
-  }
+  __syncthreads();
 }
 
+// Block LU (unit block-lower L, block-upper U with full 2x2 pivots) on the
+// fixed pattern, right-looking by levels with owner-computes rows: at level h
+// every row with a pivot k finished at level h-1 applies
+//   L_ak = A_ak U_kk^-1,  A_aj -= L_ak U_kj  (j in U(k,>k)),  y_a -= L_ak y_k
+// (the last term is the fused forward solve), and a row whose last pivot is
+// in inverts its own pivot block.  A row's entry A_ak is final when step k
+// runs because every pivot that updates it sits at a lower level.  The G
+// lanes of a task share one row (lane = scenario + S * entry) and belong to
+// one wavefront, whose LDS operations complete in program order, so a value
+// one lane writes in one step is seen by every lane in the next.  W is the
+// row: in place in an LDS-resident slice, a staging copy in LDS otherwise.
 template <typename T, int S, bool RES>
 __device__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, T* wsp, int tid, int nt,
-                             int gmin, int wstride, bool fill, bool fwd, int* piv) {
+                             int gmin, int wstride, bool fwd, int* piv) {
   for (int lev = 0; lev < D.nlev_l; ++lev) {
-    const int r0 = m.lev_l_ptr[lev], r1 = m.lev_l_ptr[lev + 1];
-    const int G = pick_group(r1 - r0, nt, gmin);
-    const int gid = tid / G, lane = tid % G, ng = nt / G;
-    for (int ri = r0 + gid; ri < r1; ri += ng) {
-      const int a = m.lev_l_rows[ri];
-      T* W = RES ? c.lu + sB<S>(m.rp[a], 0) : wsp + (size_t)gid * wstride;
-      factor_row<T, S, RES>(m, c, a, lane, G, W, fill, fwd, piv);
+    const int t0 = m.task_ptr[lev], t1 = m.task_ptr[lev + 1];
+    const Grp g = groups(t1 - t0, tid, nt, gmin);
+    const int s = g.lane % S, e = g.lane / S, E = g.G / S;
+    for (int ti = t0 + g.gid; ti < t1; ti += g.ng) {
+      const int4 tk = m.task4[ti];
+      const int a = tk.x;
+      const int rs = m.rp[a];
+      T* W;
+      if (RES) {
+        W = c.lu + sB<S>(rs, 0);
+      } else {
+        W = wsp + (size_t)g.gid * wstride;
+        const int len = m.rp[a + 1] - rs;
+        for (int q = e; q < len; q += E) st_blk(W + sB<S>(q, s), ld_blk(c.lu + sB<S>(rs + q, s)));
+      }
+      T y0 = T(0), y1 = T(0);
+      if (fwd) { y0 = c.y[sP<S>(a, s)]; y1 = c.y[sP<S>(a, s) + 1]; }
+      for (int i = tk.y; i < tk.z; ++i) {
+        const int4 st = m.step4[i];   // q, k, start of U(k,>k), |U(k,>k)|
+        const int ts = m.step_ts[i];
+        const int k = st.y;
+        const Blk<T> L = mul(ld_blk(W + sB<S>(st.x, s)), ld_blk(c.dinv + sB<S>(k, s)));
+        if (fwd) {
+          const T yk0 = c.y[sP<S>(k, s)], yk1 = c.y[sP<S>(k, s) + 1];
+          y0 -= L.a * yk0 + L.b * yk1;
+          y1 -= L.c * yk0 + L.d * yk1;
+        }
+        for (int t = e; t < st.w; t += E) {
+          const Blk<T> U = ld_blk(c.lu + sB<S>(st.z + t, s));
+          T* w = W + sB<S>(m.upd_tgt[ts + t], s);
+          Blk<T> x = ld_blk(w);
+          const Blk<T> LU = mul(L, U);
+          x.a -= LU.a; x.b -= LU.b; x.c -= LU.c; x.d -= LU.d;
+          st_blk(w, x);
+        }
+        if (e == 0) st_blk(W + sB<S>(st.x, s), L);
+      }
+      if (e == 0) {
+        if (tk.w) {
+          const Blk<T> Dk = ld_blk(W + sB<S>(m.diag[a] - rs, s));
+          const T det = Dk.a * Dk.d - Dk.b * Dk.c;
+          const T inv = T(1) / det;
+          const Blk<T> Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
+          // pivots of the block: a, then the Schur complement d - c b / a
+          const T p1 = Dk.a, p2 = det / Dk.a;
+          const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
+          const bool zero = !(fabs(p1) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
+                            !(fabs(p2) > eps * (fabs(Dk.c) + fabs(Dk.d))) || !isfinite(inv);
+          if (zero) piv[s] = 1;
+          st_blk(c.dinv + sB<S>(a, s), Di);
+        }
+        if (fwd) { c.y[sP<S>(a, s)] = y0; c.y[sP<S>(a, s) + 1] = y1; }
+      }
+      if (!RES) {
+        const int len = m.rp[a + 1] - rs;
+        for (int q = e; q < len; q += E) st_blk(c.lu + sB<S>(rs + q, s), ld_blk(W + sB<S>(q, s)));
+      }
     }
     __syncthreads();
   }
@@ -303,10 +328,10 @@ template <typename T, int S>
 __device__ void phase_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
   for (int lev = 0; lev < D.nlev_l; ++lev) {
     const int r0 = m.lev_l_ptr[lev], r1 = m.lev_l_ptr[lev + 1];
-    const int G = pick_group(r1 - r0, nt, gmin);
-    const int gid = tid / G, lane = tid % G, ng = nt / G;
-    const int s = lane % S, e = lane / S, E = G / S;
-    for (int ri = r0 + gid; ri < r1; ri += ng) {
+    const Grp g = groups(r1 - r0, tid, nt, gmin);
+    const int G = g.G;
+    const int s = g.lane % S, e = g.lane / S, E = G / S;
+    for (int ri = r0 + g.gid; ri < r1; ri += g.ng) {
       const int a = m.lev_l_rows[ri];
       T s0 = T(0), s1 = T(0);
       for (int p = m.rp[a] + e; p < m.diag[a]; p += E) {
@@ -329,10 +354,10 @@ template <typename T, int S>
 __device__ void phase_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
   for (int lev = 0; lev < D.nlev_u; ++lev) {
     const int r0 = m.lev_u_ptr[lev], r1 = m.lev_u_ptr[lev + 1];
-    const int G = pick_group(r1 - r0, nt, gmin);
-    const int gid = tid / G, lane = tid % G, ng = nt / G;
-    const int s = lane % S, e = lane / S, E = G / S;
-    for (int ri = r0 + gid; ri < r1; ri += ng) {
+    const Grp g = groups(r1 - r0, tid, nt, gmin);
+    const int G = g.G;
+    const int s = g.lane % S, e = g.lane / S, E = G / S;
+    for (int ri = r0 + g.gid; ri < r1; ri += g.ng) {
       const int a = m.lev_u_rows[ri];
       T s0 = T(0), s1 = T(0);
       for (int p = m.diag[a] + 1 + e; p < m.rp[a + 1]; p += E) {
@@ -360,9 +385,9 @@ template <typename T>
 __device__ void phase_ut_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
   for (int lev = 0; lev < D.nlev_l; ++lev) {
     const int r0 = m.lev_l_ptr[lev], r1 = m.lev_l_ptr[lev + 1];
-    const int G = pick_group(r1 - r0, nt, gmin);
-    const int gid = tid / G, lane = tid % G, ng = nt / G;
-    for (int ri = r0 + gid; ri < r1; ri += ng) {
+    const Grp g = groups(r1 - r0, tid, nt, gmin);
+    const int G = g.G, lane = g.lane;
+    for (int ri = r0 + g.gid; ri < r1; ri += g.ng) {
       const int a = m.lev_l_rows[ri];
       T s0 = T(0), s1 = T(0);
       for (int p = m.rp[a] + lane; p < m.diag[a]; p += G) {
@@ -390,9 +415,9 @@ template <typename T>
 __device__ void phase_lt_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
   for (int lev = 0; lev < D.nlev_u; ++lev) {
     const int r0 = m.lev_u_ptr[lev], r1 = m.lev_u_ptr[lev + 1];
-    const int G = pick_group(r1 - r0, nt, gmin);
-    const int gid = tid / G, lane = tid % G, ng = nt / G;
-    for (int ri = r0 + gid; ri < r1; ri += ng) {
+    const Grp g = groups(r1 - r0, tid, nt, gmin);
+    const int G = g.G, lane = g.lane;
+    for (int ri = r0 + g.gid; ri < r1; ri += g.ng) {
       const int a = m.lev_u_rows[ri];
       T s0 = T(0), s1 = T(0);
       for (int p = m.diag[a] + 1 + lane; p < m.rp[a + 1]; p += G) {
@@ -609,8 +634,8 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
     if (kp.mode == MODE_EVAL_MISMATCH || kp.mode == MODE_EVAL_FACTOR) break;
     if (!act) break;
     for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
-    __syncthreads();
-    phase_factor<T, S, RES>(m, D, c, wsp, tid, nt, gmin, kp.wstride, true, true, piv);
+    phase_fill<T, S>(m, D, c, tid, nt);
+    phase_factor<T, S, RES>(m, D, c, wsp, tid, nt, gmin, kp.wstride, true, piv);
 #pragma unroll
     for (int s = 0; s < S; ++s)
       if (((act >> s) & 1) && piv[s]) { status[s] = 3; act &= ~(1 << s); }
@@ -684,9 +709,10 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
   // keep the converged state and the factors of J1 at it for the adjoint
   const bool keep = (kp.mode == MODE_SOLVE && kp.keep) || kp.mode == MODE_EVAL_FACTOR;
   if (keep) {
-    if (tid < S) piv[tid] = 0;
     __syncthreads();
-    phase_factor<T, S, RES>(m, D, c, wsp, tid, nt, gmin, kp.wstride, true, false, piv);
+    if (tid < S) piv[tid] = 0;
+    phase_fill<T, S>(m, D, c, tid, nt);
+    phase_factor<T, S, RES>(m, D, c, wsp, tid, nt, gmin, kp.wstride, false, piv);
 #pragma unroll
     for (int s = 0; s < S; ++s)
       if (status[s] == 0 && piv[s]) status[s] = 3;

@@ -276,6 +276,53 @@ int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
       int32_t yo = find_sorted(&S.y_ci[S.y_rp[bi]], &S.y_ci[0] + S.y_rp[bi + 1], bj);
       S.lu_src[p] = yo < 0 ? -1 : S.y_rp[bi] + yo;
     }
+  // ---- factorisation tasks: steps grouped by (row, level of the pivot)
+  S.task_ptr.assign(nl + 1, 0);
+  S.task4.clear();
+  S.step4.clear();
+  S.step_ts.clear();
+  {
+    std::vector<std::vector<int32_t>> by_level(nl);   // rows with work at each level
+    for (int32_t a = 0; a < nb; ++a) {
+      if (S.diag[a] == S.rp[a]) by_level[0].push_back(a);
+      for (int32_t p = S.rp[a]; p < S.diag[a]; ++p) {
+        const int32_t h = lev_l[S.ci[p]] + 1;
+        auto& v = by_level[h];
+        if (v.empty() || v.back() != a) v.push_back(a);
+      }
+    }
+    for (int32_t h = 0; h < nl; ++h) {
+      S.task_ptr[h] = (int32_t)(S.task4.size() / 4);
+      for (int32_t a : by_level[h]) {
+        const int32_t sb = (int32_t)S.step_ts.size();
+        for (int32_t p = S.rp[a]; p < S.diag[a]; ++p) {
+          const int32_t k = S.ci[p];
+          if (lev_l[k] + 1 != h) continue;
+          S.step4.push_back(p - S.rp[a]);
+          S.step4.push_back(k);
+          S.step4.push_back(S.diag[k] + 1);
+          S.step4.push_back(S.rp[k + 1] - S.diag[k] - 1);
+          S.step_ts.push_back(S.upd_start[p]);
+        }
+        S.task4.push_back(a);
+        S.task4.push_back(sb);
+        S.task4.push_back((int32_t)S.step_ts.size());
+        S.task4.push_back(lev_l[a] == h ? 1 : 0);
+      }
+    }
+    S.task_ptr[nl] = (int32_t)(S.task4.size() / 4);
+  }
+  // ---- Jacobian fill records
+  S.fill4.resize(4 * (size_t)nnzb);
+  for (int32_t p = 0; p < nnzb; ++p) {
+    const int32_t a = S.prow[p], j = S.ci[p];
+    const int32_t bi = S.blk_bus[a], bj = S.blk_bus[j];
+    int32_t fl = (a == j ? 1 : 0) | (bus_type[bi] == PF_BUS_PV ? 2 : 0) | (bus_type[bj] == PF_BUS_PV ? 4 : 0);
+    S.fill4[4 * p] = S.lu_src[p];
+    S.fill4[4 * p + 1] = bi;
+    S.fill4[4 * p + 2] = bj;
+    S.fill4[4 * p + 3] = fl;
+  }
   // ---- statistics
   auto nun = [&](int32_t bus) { return bus_type[bus] == PF_BUS_PQ ? 2 : 1; };
   S.nnz_j1 = 0;

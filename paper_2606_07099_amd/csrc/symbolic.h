@@ -49,8 +49,20 @@ struct Symbolic {
   std::vector<int32_t> upd_tgt;      // row-relative block offsets inside row a
 
   // level schedules
-  std::vector<int32_t> lev_l_ptr, lev_l_rows;   // factor / forward solve / U^T solve
+  std::vector<int32_t> lev_l_ptr, lev_l_rows;   // forward solve / U^T solve
   std::vector<int32_t> lev_u_ptr, lev_u_rows;   // backward solve / L^T solve
+
+  // factorisation schedule, right-looking by levels with owner-computes rows:
+  // at level h each row applies the elimination steps whose pivot row was
+  // finished at level h-1 and, once its last pivot is in, inverts its own
+  // pivot block.  Tasks of one level touch distinct rows.
+  std::vector<int32_t> task_ptr;  // [n_levels_l + 1]
+  std::vector<int32_t> task4;     // [n_tasks][4]: row a, first step, end step, finalise flag
+  std::vector<int32_t> step4;     // [n_steps][4]: q = L position - rp[a], k, start of U(k,>k), |U(k,>k)|
+  std::vector<int32_t> step_ts;   // [n_steps]: first entry of the step's targets in upd_tgt
+  // Jacobian fill record of every block: Y_bus entry (-1: fill-in), bus of
+  // the row, bus of the column, flags (1 diagonal, 2 row bus PV, 4 column bus PV)
+  std::vector<int32_t> fill4;     // [nnzb][4]
 
   // statistics
   int64_t nnz_j1 = 0;        // scalar nonzeros of J1 (real unknowns only)
