@@ -275,8 +275,10 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   so.task4 = (int)pk.add(S.task4); so.step4 = (int)pk.add(S.step4);
   so.step_ts = (int)pk.add(S.step_ts); so.upd_tgt = (int)pk.add(S.upd_tgt);
   so.lev_l_ptr = (int)pk.add(S.lev_l_ptr); so.lev_l_rows = (int)pk.add(S.lev_l_rows);
-  so.lev_u_ptr = (int)pk.add(S.lev_u_ptr); so.lev_u_rows = (int)pk.add(S.lev_u_rows);
+  so.lev_um_ptr = (int)pk.add(S.lev_um_ptr); so.lev_um_rows = (int)pk.add(S.lev_um_rows);
+  so.tail_pos = (int)pk.add(S.tail_pos); so.tail_split = (int)pk.add(S.tail_split);
   so.newton_bytes = (int)pk.align();
+  so.lev_u_ptr = (int)pk.add(S.lev_u_ptr); so.lev_u_rows = (int)pk.add(S.lev_u_rows);
   so.blk_bus = (int)pk.add(S.blk_bus); so.lu_src = (int)pk.add(S.lu_src);
   so.mirror = (int)pk.add(S.mirror); so.y_tr = (int)pk.add(S.y_tr);
   so.ord_p = (int)pk.add(ord_p); so.ord_q = (int)pk.add(ord_q);
@@ -284,6 +286,9 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   sable::Dims& dm = t->dims;
   dm.n_bus = S.n_bus; dm.nb = S.nb; dm.nnzb = S.nnzb(); dm.nj = S.nb + S.n_pq; dm.npq = S.n_pq;
   dm.npvpq = S.nb; dm.nlev_l = S.n_levels_l(); dm.nlev_u = S.n_levels_u();
+  dm.nlev_f = S.n_task_levels; dm.nlev_fs = S.n_fs_levels;
+  dm.nlev_bs = (int)S.lev_um_ptr.size() - 1;
+  dm.tail_t = S.tail_t; dm.tail_base = S.tail_base;
 
   // ---- launch shape: LDS-resident slices of S scenarios when they fit,
   // choosing S to maximise the scenarios resident per CU; HBM-resident

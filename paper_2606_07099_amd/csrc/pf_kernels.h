@@ -32,14 +32,18 @@ constexpr int kScratchBytes = 2048;
 struct SymOffsets {
   int bus_type, bus_blk, y_rp, y_ci, y_g, y_b;
   int rp, ci, diag, fill4, task_ptr, task4, step4, step_ts, upd_tgt;
-  int lev_l_ptr, lev_l_rows, lev_u_ptr, lev_u_rows;
+  int lev_l_ptr, lev_l_rows, lev_um_ptr, lev_um_rows, tail_pos, tail_split;
   int newton_bytes;
+  int lev_u_ptr, lev_u_rows;
   int blk_bus, lu_src, mirror, y_tr, ord_p, ord_q;
   int total_bytes;
 };
 
 struct Dims {
-  int n_bus, nb, nnzb, nj, npq, npvpq, nlev_l, nlev_u;
+  int n_bus, nb, nnzb, nj, npq, npvpq;
+  int nlev_l, nlev_u;             // full level schedules (adjoint)
+  int nlev_f, nlev_fs, nlev_bs;   // factor-task, forward and backward levels outside the tail
+  int tail_t, tail_base;          // dense tail rows [tail_base, tail_base + tail_t)
 };
 
 // Offsets of the per-scenario arrays, in elements.  FP64 arrays:

@@ -52,6 +52,7 @@ struct Sym {
   const int4 *fill4, *task4, *step4;
   const int *task_ptr, *step_ts, *upd_tgt;
   const int *lev_l_ptr, *lev_l_rows, *lev_u_ptr, *lev_u_rows;
+  const int *lev_um_ptr, *lev_um_rows, *tail_pos, *tail_split;
   const int *blk_bus, *lu_src, *mirror, *y_tr, *ord_p, *ord_q;
 };
 
@@ -75,8 +76,12 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
   m.upd_tgt = reinterpret_cast<const int*>(nb + o.upd_tgt);
   m.lev_l_ptr = reinterpret_cast<const int*>(nb + o.lev_l_ptr);
   m.lev_l_rows = reinterpret_cast<const int*>(nb + o.lev_l_rows);
-  m.lev_u_ptr = reinterpret_cast<const int*>(nb + o.lev_u_ptr);
-  m.lev_u_rows = reinterpret_cast<const int*>(nb + o.lev_u_rows);
+  m.lev_um_ptr = reinterpret_cast<const int*>(nb + o.lev_um_ptr);
+  m.lev_um_rows = reinterpret_cast<const int*>(nb + o.lev_um_rows);
+  m.tail_pos = reinterpret_cast<const int*>(nb + o.tail_pos);
+  m.tail_split = reinterpret_cast<const int*>(nb + o.tail_split);
+  m.lev_u_ptr = reinterpret_cast<const int*>(g + o.lev_u_ptr);
+  m.lev_u_rows = reinterpret_cast<const int*>(g + o.lev_u_rows);
   m.blk_bus = reinterpret_cast<const int*>(g + o.blk_bus);
   m.lu_src = reinterpret_cast<const int*>(g + o.lu_src);
   m.mirror = reinterpret_cast<const int*>(g + o.mirror);
@@ -260,7 +265,7 @@ __device__ void phase_fill(const Sym& m, const Dims& D, St<T>& c, int tid, int n
 template <typename T, int S, bool RES>
 __device__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, T* wsp, int tid, int nt,
                              int gmin, int wstride, bool fwd, int* piv) {
-  for (int lev = 0; lev < D.nlev_l; ++lev) {
+  for (int lev = 0; lev < D.nlev_f; ++lev) {
     const int t0 = m.task_ptr[lev], t1 = m.task_ptr[lev + 1];
     const Grp g = groups(t1 - t0, tid, nt, gmin);
     const int s = g.lane % S, e = g.lane / S, E = g.G / S;
@@ -326,7 +331,7 @@ __device__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, T* wsp, int 
 // L y = y (unit block-lower, in place) by L-levels
 template <typename T, int S>
 __device__ void phase_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
-  for (int lev = 0; lev < D.nlev_l; ++lev) {
+  for (int lev = 0; lev < D.nlev_fs; ++lev) {
     const int r0 = m.lev_l_ptr[lev], r1 = m.lev_l_ptr[lev + 1];
     const Grp g = groups(r1 - r0, tid, nt, gmin);
     const int G = g.G;
@@ -349,16 +354,17 @@ __device__ void phase_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int
   }
 }
 
-// U x = y (block-upper with full diagonal blocks, in place) by U-levels
+// U x = y (block-upper with full diagonal blocks, in place) by U-levels, for
+// the rows outside the dense tail (whose unknowns are solved first)
 template <typename T, int S>
 __device__ void phase_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
-  for (int lev = 0; lev < D.nlev_u; ++lev) {
-    const int r0 = m.lev_u_ptr[lev], r1 = m.lev_u_ptr[lev + 1];
+  for (int lev = 0; lev < D.nlev_bs; ++lev) {
+    const int r0 = m.lev_um_ptr[lev], r1 = m.lev_um_ptr[lev + 1];
     const Grp g = groups(r1 - r0, tid, nt, gmin);
     const int G = g.G;
     const int s = g.lane % S, e = g.lane / S, E = G / S;
     for (int ri = r0 + g.gid; ri < r1; ri += g.ng) {
-      const int a = m.lev_u_rows[ri];
+      const int a = m.lev_um_rows[ri];
       T s0 = T(0), s1 = T(0);
       for (int p = m.diag[a] + 1 + e; p < m.rp[a + 1]; p += E) {
         const Blk<T> U = ld_blk(c.lu + sB<S>(p, s));
@@ -432,6 +438,160 @@ __device__ void phase_lt_solve(const Sym& m, const Dims& D, St<T>& c, int tid, i
       if (lane == 0) { c.y[2 * a] -= s0; c.y[2 * a + 1] -= s1; }
     }
     __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// dense tail: the top rows of the elimination tree, one wavefront per
+// scenario, ordered by the in-order completion of a wavefront's memory
+// operations (no workgroup barrier inside)
+
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// orders this wavefront's earlier global stores before its later loads (HBM
+// state); LDS operations of a wavefront are already in order
+template <bool RES>
+__device__ __forceinline__ void wave_order() {
+  if (!RES) __threadfence_block();
+}
+
+// LU of the tail block, pivots in row order: lane k inverts its pivot block,
+// the lanes below form their multipliers (and apply them to the right-hand
+// side), and (row, column-chunk) lanes update the trailing block.
+template <typename T, int S, bool RES>
+__device__ void phase_tail_factor(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, bool fwd,
+                                  int* piv) {
+  const int t = D.tail_t, tb = D.tail_base;
+  const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
+  for (int s = w; s < S; s += nw) {
+    T y0 = T(0), y1 = T(0);
+    if (fwd && l < t) { y0 = c.y[sP<S>(tb + l, s)]; y1 = c.y[sP<S>(tb + l, s) + 1]; }
+    for (int k = 0; k < t; ++k) {
+      Blk<T> Di = {T(0), T(0), T(0), T(0)};
+      if (l == k) {
+        const Blk<T> Dk = ld_blk(c.lu + sB<S>(m.tail_pos[k * t + k], s));
+        const T det = Dk.a * Dk.d - Dk.b * Dk.c;
+        const T inv = T(1) / det;
+        Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
+        const T p1 = Dk.a, p2 = det / Dk.a;
+        const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
+        const bool zero = !(fabs(p1) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
+                          !(fabs(p2) > eps * (fabs(Dk.c) + fabs(Dk.d))) || !isfinite(inv);
+        if (zero) piv[s] = 1;
+        st_blk(c.dinv + sB<S>(tb + k, s), Di);
+      }
+      Di = {lane_bcast(Di.a, k), lane_bcast(Di.b, k), lane_bcast(Di.c, k), lane_bcast(Di.d, k)};
+      const T yk0 = lane_bcast(y0, k), yk1 = lane_bcast(y1, k);
+      // multipliers L_ik = A_ik U_kk^-1 for the rows below
+      if (l > k && l < t) {
+        const int pik = m.tail_pos[l * t + k];
+        if (pik >= 0) {
+          const Blk<T> L = mul(ld_blk(c.lu + sB<S>(pik, s)), Di);
+          st_blk(c.lu + sB<S>(pik, s), L);
+          y0 -= L.a * yk0 + L.b * yk1;
+          y1 -= L.c * yk0 + L.d * yk1;
+        }
+      }
+      wave_order<RES>();
+      // trailing block: A_ij -= L_ik U_kj, rows k+1.. split into column chunks
+      const int mr = t - k - 1;
+      if (mr > 0) {
+        int cpr = 1;
+        while (cpr * 2 * mr <= 64) cpr *= 2;
+        const int lg = __builtin_ctz(cpr);
+        const int i = k + 1 + (l >> lg);
+        if (i < t) {
+          const int pik = m.tail_pos[i * t + k];
+          if (pik >= 0) {
+            const Blk<T> L = ld_blk(c.lu + sB<S>(pik, s));
+            for (int j = k + 1 + (l & (cpr - 1)); j < t; j += cpr) {
+              const int pkj = m.tail_pos[k * t + j];
+              if (pkj < 0) continue;
+              T* a = c.lu + sB<S>(m.tail_pos[i * t + j], s);
+              Blk<T> x = ld_blk(a);
+              const Blk<T> LU = mul(L, ld_blk(c.lu + sB<S>(pkj, s)));
+              x.a -= LU.a; x.b -= LU.b; x.c -= LU.c; x.d -= LU.d;
+              st_blk(a, x);
+            }
+          }
+        }
+      }
+      wave_order<RES>();
+    }
+    if (fwd && l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+  }
+}
+
+// forward solve of the tail rows: their terms on rows outside the tail,
+// then the unit block-lower tail block, broadcasting each finished unknown
+template <typename T, int S, bool RES>
+__device__ void phase_tail_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+  const int t = D.tail_t, tb = D.tail_base;
+  const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
+  for (int s = w; s < S; s += nw) {
+    T y0 = T(0), y1 = T(0);
+    if (l < t) {
+      const int a = tb + l;
+      y0 = c.y[sP<S>(a, s)];
+      y1 = c.y[sP<S>(a, s) + 1];
+      for (int p = m.rp[a]; p < m.tail_split[l]; ++p) {
+        const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
+        const int k = m.ci[p];
+        const T z0 = c.y[sP<S>(k, s)], z1 = c.y[sP<S>(k, s) + 1];
+        y0 -= L.a * z0 + L.b * z1;
+        y1 -= L.c * z0 + L.d * z1;
+      }
+    }
+    for (int j = 0; j < t; ++j) {
+      const T yj0 = lane_bcast(y0, j), yj1 = lane_bcast(y1, j);
+      if (l > j && l < t) {
+        const int p = m.tail_pos[l * t + j];
+        if (p >= 0) {
+          const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
+          y0 -= L.a * yj0 + L.b * yj1;
+          y1 -= L.c * yj0 + L.d * yj1;
+        }
+      }
+    }
+    if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+  }
+}
+
+// backward solve of the tail block (its rows only couple to tail columns):
+// the last unknown first, each finished one broadcast to the rows above
+template <typename T, int S, bool RES>
+__device__ void phase_tail_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+  const int t = D.tail_t, tb = D.tail_base;
+  const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
+  for (int s = w; s < S; s += nw) {
+    T y0 = T(0), y1 = T(0);
+    if (l < t) { y0 = c.y[sP<S>(tb + l, s)]; y1 = c.y[sP<S>(tb + l, s) + 1]; }
+    for (int j = t - 1; j >= 0; --j) {
+      if (l == j) {
+        const Blk<T> Di = ld_blk(c.dinv + sB<S>(tb + j, s));
+        const T x0 = Di.a * y0 + Di.b * y1, x1 = Di.c * y0 + Di.d * y1;
+        y0 = x0;
+        y1 = x1;
+      }
+      const T xj0 = lane_bcast(y0, j), xj1 = lane_bcast(y1, j);
+      if (l < j) {
+        const int p = m.tail_pos[l * t + j];
+        if (p >= 0) {
+          const Blk<T> U = ld_blk(c.lu + sB<S>(p, s));
+          y0 -= U.a * xj0 + U.b * xj1;
+          y1 -= U.c * xj0 + U.d * xj1;
+        }
+      }
+    }
+    if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
   }
 }
 
@@ -636,10 +796,14 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
     for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
     phase_fill<T, S>(m, D, c, tid, nt);
     phase_factor<T, S, RES>(m, D, c, wsp, tid, nt, gmin, kp.wstride, true, piv);
+    phase_tail_factor<T, S, RES>(m, D, c, tid, nt, true, piv);
+    __syncthreads();
 #pragma unroll
     for (int s = 0; s < S; ++s)
       if (((act >> s) & 1) && piv[s]) { status[s] = 3; act &= ~(1 << s); }
     if (!act) break;
+    phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
+    __syncthreads();
     phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
     for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
     __syncthreads();
@@ -648,6 +812,10 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
         phase_dv<T, S>(m, D, c, tid, nt);
         phase_residual<T, S>(m, D, c, tid, nt);
         phase_fsolve<T, S>(m, D, c, tid, nt, gmin);
+        phase_tail_fsolve<T, S, RES>(m, D, c, tid, nt);
+        __syncthreads();
+        phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
+        __syncthreads();
         phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
         for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] += double(c.y[q]);
         __syncthreads();
@@ -713,6 +881,8 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
     if (tid < S) piv[tid] = 0;
     phase_fill<T, S>(m, D, c, tid, nt);
     phase_factor<T, S, RES>(m, D, c, wsp, tid, nt, gmin, kp.wstride, false, piv);
+    phase_tail_factor<T, S, RES>(m, D, c, tid, nt, false, piv);
+    __syncthreads();
 #pragma unroll
     for (int s = 0; s < S; ++s)
       if (status[s] == 0 && piv[s]) status[s] = 3;

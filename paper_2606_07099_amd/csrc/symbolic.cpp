@@ -91,7 +91,7 @@ int ybus_from_branches(int32_t n_bus, int32_t n_branch, const int32_t* f, const 
 
 int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
             const int32_t* y_indices, const double* y_g, const double* y_b, Symbolic& S,
-            std::string& err) {
+            std::string& err, int32_t tail_max) {
   if (n_bus < 2 || !bus_type || !y_indptr || !y_indices || !y_g || !y_b) {
     err = "template: need n_bus >= 2 and non-null bus_type / Y_bus arrays";
     return PF_EINVAL;
@@ -191,6 +191,20 @@ int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
     for (int32_t u : cl) merge_into(adj[u], cl, v, u, tmp);
     adj[v].clear();
   }
+  // ---- renumber by (elimination-tree level, elimination position): a
+  // topological order of the same elimination tree, hence the same fill,
+  // with the highest levels (the top separator) last
+  {
+    std::vector<int32_t> lvl(nb, 0), pos(nb);
+    for (int32_t r = 0; r < nb; ++r) pos[order[r]] = r;
+    for (int32_t r = 0; r < nb; ++r) {
+      const int32_t v = order[r];
+      for (int32_t u : later[v]) lvl[u] = std::max(lvl[u], lvl[v] + 1);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+      return lvl[x] != lvl[y] ? lvl[x] < lvl[y] : pos[x] < pos[y];
+    });
+  }
   // ---- block rows in elimination order
   std::vector<int32_t> iperm(nb);
   for (int32_t r = 0; r < nb; ++r) iperm[order[r]] = r;
@@ -276,8 +290,37 @@ int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
       int32_t yo = find_sorted(&S.y_ci[S.y_rp[bi]], &S.y_ci[0] + S.y_rp[bi + 1], bj);
       S.lu_src[p] = yo < 0 ? -1 : S.y_rp[bi] + yo;
     }
-  // ---- factorisation tasks: steps grouped by (row, level of the pivot)
-  S.task_ptr.assign(nl + 1, 0);
+  // ---- dense tail: the rows of the highest levels, at most tail_max of them
+  {
+    std::vector<int32_t> cnt(nl + 1, 0);
+    for (int32_t a = 0; a < nb; ++a) cnt[lev_l[a]]++;
+    int32_t h = nl, t = 0;
+    while (h > 0 && t + cnt[h - 1] <= std::min<int32_t>(tail_max, 64)) { t += cnt[h - 1]; --h; }
+    if (t < 4) { t = 0; h = nl; }
+    S.tail_t = t;
+    S.tail_h = h;
+    S.tail_base = nb - t;
+    for (int32_t a = 0; a < nb; ++a)
+      if ((a >= S.tail_base) != (lev_l[a] >= h)) { err = "template: internal error, tail rows not last"; return PF_EINVAL; }
+    S.tail_pos.assign((size_t)t * t, -1);
+    S.tail_split.assign(t, 0);
+    for (int32_t i = 0; i < t; ++i) {
+      const int32_t a = S.tail_base + i;
+      S.tail_split[i] = S.rp[a];
+      for (int32_t p = S.rp[a]; p < S.rp[a + 1]; ++p) {
+        if (S.ci[p] < S.tail_base) { S.tail_split[i] = p + 1; continue; }
+        S.tail_pos[(size_t)i * t + (S.ci[p] - S.tail_base)] = p;
+      }
+    }
+  }
+  const int32_t tb = S.tail_base;
+  // ---- factorisation tasks of the barrier-synchronised part: steps grouped
+  // by (row, level of the pivot); pivots inside the tail and the tail's own
+  // pivot blocks are left to the dense tail
+  S.n_task_levels = S.tail_t ? std::min(S.tail_h + 1, nl) : nl;
+  S.n_fs_levels = S.tail_t ? S.tail_h : nl;
+  const int32_t ntl = S.n_task_levels;
+  S.task_ptr.assign(ntl + 1, 0);
   S.task4.clear();
   S.step4.clear();
   S.step_ts.clear();
@@ -291,26 +334,46 @@ int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
         if (v.empty() || v.back() != a) v.push_back(a);
       }
     }
-    for (int32_t h = 0; h < nl; ++h) {
+    for (int32_t h = 0; h < ntl; ++h) {
       S.task_ptr[h] = (int32_t)(S.task4.size() / 4);
       for (int32_t a : by_level[h]) {
         const int32_t sb = (int32_t)S.step_ts.size();
         for (int32_t p = S.rp[a]; p < S.diag[a]; ++p) {
           const int32_t k = S.ci[p];
-          if (lev_l[k] + 1 != h) continue;
+          if (lev_l[k] + 1 != h || k >= tb) continue;
           S.step4.push_back(p - S.rp[a]);
           S.step4.push_back(k);
           S.step4.push_back(S.diag[k] + 1);
           S.step4.push_back(S.rp[k + 1] - S.diag[k] - 1);
           S.step_ts.push_back(S.upd_start[p]);
         }
+        const int32_t fin = (lev_l[a] == h && a < tb) ? 1 : 0;
+        if ((int32_t)S.step_ts.size() == sb && !fin) continue;
         S.task4.push_back(a);
         S.task4.push_back(sb);
         S.task4.push_back((int32_t)S.step_ts.size());
-        S.task4.push_back(lev_l[a] == h ? 1 : 0);
+        S.task4.push_back(fin);
       }
     }
-    S.task_ptr[nl] = (int32_t)(S.task4.size() / 4);
+    S.task_ptr[ntl] = (int32_t)(S.task4.size() / 4);
+  }
+  // ---- backward-solve levels of the rows outside the tail
+  {
+    std::vector<int32_t> lv(nb, 0);
+    int32_t nlu = 0;
+    for (int32_t a = tb - 1; a >= 0; --a) {
+      int32_t x = 0;
+      for (int32_t p = S.diag[a] + 1; p < S.rp[a + 1]; ++p)
+        if (S.ci[p] < tb) x = std::max(x, lv[S.ci[p]] + 1);
+      lv[a] = x;
+      nlu = std::max(nlu, x + 1);
+    }
+    S.lev_um_ptr.assign(nlu + 1, 0);
+    for (int32_t a = 0; a < tb; ++a) S.lev_um_ptr[lv[a] + 1]++;
+    for (int32_t l = 0; l < nlu; ++l) S.lev_um_ptr[l + 1] += S.lev_um_ptr[l];
+    S.lev_um_rows.resize(tb);
+    std::vector<int32_t> fp(S.lev_um_ptr.begin(), S.lev_um_ptr.end() - 1);
+    for (int32_t a = 0; a < tb; ++a) S.lev_um_rows[fp[lv[a]]++] = a;
   }
   // ---- Jacobian fill records
   S.fill4.resize(4 * (size_t)nnzb);

@@ -60,6 +60,17 @@ struct Symbolic {
   std::vector<int32_t> task4;     // [n_tasks][4]: row a, first step, end step, finalise flag
   std::vector<int32_t> step4;     // [n_steps][4]: q = L position - rp[a], k, start of U(k,>k), |U(k,>k)|
   std::vector<int32_t> step_ts;   // [n_steps]: first entry of the step's targets in upd_tgt
+  // dense tail: the last tail_t block rows (the top of the elimination tree,
+  // highest levels) are factorised and solved by one wavefront per scenario
+  // without workgroup barriers.  tail_pos[i*t + j] is the position of block
+  // (tail_base + i, tail_base + j) or -1; tail_split[i] the first position of
+  // tail row i whose column lies in the tail.  task_ptr covers the levels of
+  // the barrier-synchronised part only; lev_um_* are the backward-solve
+  // levels of the rows outside the tail.
+  int32_t tail_t = 0, tail_base = 0, tail_h = 0;
+  int32_t n_task_levels = 0, n_fs_levels = 0;
+  std::vector<int32_t> tail_pos, tail_split;
+  std::vector<int32_t> lev_um_ptr, lev_um_rows;
   // Jacobian fill record of every block: Y_bus entry (-1: fill-in), bus of
   // the row, bus of the column, flags (1 diagonal, 2 row bus PV, 4 column bus PV)
   std::vector<int32_t> fill4;     // [nnzb][4]
@@ -78,9 +89,10 @@ struct Symbolic {
 };
 
 // Returns 0 on success; on failure a negative PF_E* code and a message.
+// tail_max: largest dense tail (0 disables it; at most 64)
 int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
             const int32_t* y_indices, const double* y_g, const double* y_b,
-            Symbolic& out, std::string& err);
+            Symbolic& out, std::string& err, int32_t tail_max = 32);
 
 // pi-model branch admittances assembled into CSR (columns sorted, duplicate
 // branches summed).  Returns nnz, or a negative error code.
