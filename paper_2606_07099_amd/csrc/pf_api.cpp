@@ -277,6 +277,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   so.lev_l_ptr = (int)pk.add(S.lev_l_ptr); so.lev_l_rows = (int)pk.add(S.lev_l_rows);
   so.lev_um_ptr = (int)pk.add(S.lev_um_ptr); so.lev_um_rows = (int)pk.add(S.lev_um_rows);
   so.tail_pos = (int)pk.add(S.tail_pos); so.tail_split = (int)pk.add(S.tail_split);
+  so.tk_ptr = (int)pk.add(S.tk_ptr); so.tstep4 = (int)pk.add(S.tstep4);
   so.newton_bytes = (int)pk.align();
   so.lev_u_ptr = (int)pk.add(S.lev_u_ptr); so.lev_u_rows = (int)pk.add(S.lev_u_rows);
   so.blk_bus = (int)pk.add(S.blk_bus); so.lu_src = (int)pk.add(S.lu_src);

@@ -32,7 +32,7 @@ constexpr int kScratchBytes = 2048;
 struct SymOffsets {
   int bus_type, bus_blk, y_rp, y_ci, y_g, y_b;
   int rp, ci, diag, fill4, task_ptr, task4, step4, step_ts, upd_tgt;
-  int lev_l_ptr, lev_l_rows, lev_um_ptr, lev_um_rows, tail_pos, tail_split;
+  int lev_l_ptr, lev_l_rows, lev_um_ptr, lev_um_rows, tail_pos, tail_split, tk_ptr, tstep4;
   int newton_bytes;
   int lev_u_ptr, lev_u_rows;
   int blk_bus, lu_src, mirror, y_tr, ord_p, ord_q;

@@ -52,7 +52,8 @@ struct Sym {
   const int4 *fill4, *task4, *step4;
   const int *task_ptr, *step_ts, *upd_tgt;
   const int *lev_l_ptr, *lev_l_rows, *lev_u_ptr, *lev_u_rows;
-  const int *lev_um_ptr, *lev_um_rows, *tail_pos, *tail_split;
+  const int *lev_um_ptr, *lev_um_rows, *tail_pos, *tail_split, *tk_ptr;
+  const int4* tstep4;
   const int *blk_bus, *lu_src, *mirror, *y_tr, *ord_p, *ord_q;
 };
 
@@ -80,6 +81,8 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
   m.lev_um_rows = reinterpret_cast<const int*>(nb + o.lev_um_rows);
   m.tail_pos = reinterpret_cast<const int*>(nb + o.tail_pos);
   m.tail_split = reinterpret_cast<const int*>(nb + o.tail_split);
+  m.tk_ptr = reinterpret_cast<const int*>(nb + o.tk_ptr);
+  m.tstep4 = reinterpret_cast<const int4*>(nb + o.tstep4);
   m.lev_u_ptr = reinterpret_cast<const int*>(g + o.lev_u_ptr);
   m.lev_u_rows = reinterpret_cast<const int*>(g + o.lev_u_rows);
   m.blk_bus = reinterpret_cast<const int*>(g + o.blk_bus);
@@ -463,70 +466,69 @@ __device__ __forceinline__ void wave_order() {
   if (!RES) __threadfence_block();
 }
 
-// LU of the tail block, pivots in row order: lane k inverts its pivot block,
-// the lanes below form their multipliers (and apply them to the right-hand
-// side), and (row, column-chunk) lanes update the trailing block.
+// LU of the tail rows, one pivot at a time in row order: the pivot block is
+// inverted, then every tail row with a multiplier for this pivot forms it,
+// applies it to its right-hand side entry and to its targets of the pivot's
+// U row, lanes = (elimination step, entry of the U row).  Same arithmetic as
+// the barrier-synchronised tasks, one pivot per wavefront step.
 template <typename T, int S, bool RES>
 __device__ void phase_tail_factor(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, bool fwd,
                                   int* piv) {
   const int t = D.tail_t, tb = D.tail_base;
   const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
   for (int s = w; s < S; s += nw) {
-    T y0 = T(0), y1 = T(0);
-    if (fwd && l < t) { y0 = c.y[sP<S>(tb + l, s)]; y1 = c.y[sP<S>(tb + l, s) + 1]; }
     for (int k = 0; k < t; ++k) {
+      const int ak = tb + k;
+      const int dk = m.diag[ak];
       Blk<T> Di = {T(0), T(0), T(0), T(0)};
-      if (l == k) {
-        const Blk<T> Dk = ld_blk(c.lu + sB<S>(m.tail_pos[k * t + k], s));
+      if (l == 0) {
+        const Blk<T> Dk = ld_blk(c.lu + sB<S>(dk, s));
         const T det = Dk.a * Dk.d - Dk.b * Dk.c;
         const T inv = T(1) / det;
         Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
+        // pivots of the block: a, then the Schur complement d - c b / a
         const T p1 = Dk.a, p2 = det / Dk.a;
         const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
         const bool zero = !(fabs(p1) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
                           !(fabs(p2) > eps * (fabs(Dk.c) + fabs(Dk.d))) || !isfinite(inv);
         if (zero) piv[s] = 1;
-        st_blk(c.dinv + sB<S>(tb + k, s), Di);
+        st_blk(c.dinv + sB<S>(ak, s), Di);
       }
-      Di = {lane_bcast(Di.a, k), lane_bcast(Di.b, k), lane_bcast(Di.c, k), lane_bcast(Di.d, k)};
-      const T yk0 = lane_bcast(y0, k), yk1 = lane_bcast(y1, k);
-      // multipliers L_ik = A_ik U_kk^-1 for the rows below
-      if (l > k && l < t) {
-        const int pik = m.tail_pos[l * t + k];
-        if (pik >= 0) {
-          const Blk<T> L = mul(ld_blk(c.lu + sB<S>(pik, s)), Di);
-          st_blk(c.lu + sB<S>(pik, s), L);
-          y0 -= L.a * yk0 + L.b * yk1;
-          y1 -= L.c * yk0 + L.d * yk1;
-        }
-      }
-      wave_order<RES>();
-      // trailing block: A_ij -= L_ik U_kj, rows k+1.. split into column chunks
-      const int mr = t - k - 1;
-      if (mr > 0) {
-        int cpr = 1;
-        while (cpr * 2 * mr <= 64) cpr *= 2;
-        const int lg = __builtin_ctz(cpr);
-        const int i = k + 1 + (l >> lg);
-        if (i < t) {
-          const int pik = m.tail_pos[i * t + k];
-          if (pik >= 0) {
-            const Blk<T> L = ld_blk(c.lu + sB<S>(pik, s));
-            for (int j = k + 1 + (l & (cpr - 1)); j < t; j += cpr) {
-              const int pkj = m.tail_pos[k * t + j];
-              if (pkj < 0) continue;
-              T* a = c.lu + sB<S>(m.tail_pos[i * t + j], s);
-              Blk<T> x = ld_blk(a);
-              const Blk<T> LU = mul(L, ld_blk(c.lu + sB<S>(pkj, s)));
-              x.a -= LU.a; x.b -= LU.b; x.c -= LU.c; x.d -= LU.d;
-              st_blk(a, x);
+      Di = {lane_bcast(Di.a, 0), lane_bcast(Di.b, 0), lane_bcast(Di.c, 0), lane_bcast(Di.d, 0)};
+      const int t0 = m.tk_ptr[k], t1 = m.tk_ptr[k + 1];
+      if (t1 > t0) {
+        T yk0 = T(0), yk1 = T(0);
+        if (fwd) { yk0 = c.y[sP<S>(ak, s)]; yk1 = c.y[sP<S>(ak, s) + 1]; }
+        const int ks = dk + 1, n = m.rp[ak + 1] - ks;
+        int E = 1;
+        while (E < n && E < 64) E <<= 1;
+        const int lg = __builtin_ctz(E), per = 64 >> lg;
+        const int e = l & (E - 1);
+        for (int st = t0 + (l >> lg); st - (l >> lg) < t1; st += per) {
+          if (st >= t1) continue;
+          const int4 r = m.tstep4[st];   // row i, q, first target, -
+          const int rs = m.rp[r.x];
+          T* W = c.lu + sB<S>(rs, 0);
+          const Blk<T> L = mul(ld_blk(W + sB<S>(r.y, s)), Di);
+          for (int j = e; j < n; j += E) {
+            const Blk<T> U = ld_blk(c.lu + sB<S>(ks + j, s));
+            T* a = W + sB<S>(m.upd_tgt[r.z + j], s);
+            Blk<T> x = ld_blk(a);
+            const Blk<T> LU = mul(L, U);
+            x.a -= LU.a; x.b -= LU.b; x.c -= LU.c; x.d -= LU.d;
+            st_blk(a, x);
+          }
+          if (e == 0) {
+            st_blk(W + sB<S>(r.y, s), L);
+            if (fwd) {
+              c.y[sP<S>(r.x, s)] -= L.a * yk0 + L.b * yk1;
+              c.y[sP<S>(r.x, s) + 1] -= L.c * yk0 + L.d * yk1;
             }
           }
         }
       }
       wave_order<RES>();
     }
-    if (fwd && l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
   }
 }
 

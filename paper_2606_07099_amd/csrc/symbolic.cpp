@@ -314,6 +314,28 @@ int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
     }
   }
   const int32_t tb = S.tail_base;
+  {
+    const int32_t t = S.tail_t;
+    std::vector<std::vector<int32_t>> by_piv(t);
+    for (int32_t i = 0; i < t; ++i) {
+      const int32_t a = tb + i;
+      for (int32_t p = S.rp[a]; p < S.diag[a]; ++p) {
+        const int32_t k = S.ci[p];
+        if (k < tb) continue;
+        by_piv[k - tb].push_back(a);
+        by_piv[k - tb].push_back(p - S.rp[a]);
+        by_piv[k - tb].push_back(S.upd_start[p]);
+        by_piv[k - tb].push_back(0);
+      }
+    }
+    S.tk_ptr.assign(t + 1, 0);
+    S.tstep4.clear();
+    for (int32_t k = 0; k < t; ++k) {
+      S.tk_ptr[k] = (int32_t)(S.tstep4.size() / 4);
+      S.tstep4.insert(S.tstep4.end(), by_piv[k].begin(), by_piv[k].end());
+    }
+    S.tk_ptr[t] = (int32_t)(S.tstep4.size() / 4);
+  }
   // ---- factorisation tasks of the barrier-synchronised part: steps grouped
   // by (row, level of the pivot); pivots inside the tail and the tail's own
   // pivot blocks are left to the dense tail

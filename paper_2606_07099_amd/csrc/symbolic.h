@@ -70,6 +70,10 @@ struct Symbolic {
   int32_t tail_t = 0, tail_base = 0, tail_h = 0;
   int32_t n_task_levels = 0, n_fs_levels = 0;
   std::vector<int32_t> tail_pos, tail_split;
+  // elimination steps of the tail pivots, pivot by pivot: tk_ptr[k] .. tk_ptr[k+1]
+  // index tstep4 records {row i, q = L position of (i, pivot) - rp[i], first
+  // target in upd_tgt, 0}
+  std::vector<int32_t> tk_ptr, tstep4;
   std::vector<int32_t> lev_um_ptr, lev_um_rows;
   // Jacobian fill record of every block: Y_bus entry (-1: fill-in), bus of
   // the row, bus of the column, flags (1 diagonal, 2 row bus PV, 4 column bus PV)
