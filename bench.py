@@ -27,6 +27,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_amd/csrc/pf_kernels.h")
+
+# HBM bytes per launch of the mixed-precision Newton kernel on the default
+# workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE passes (each scaled by
+# the same counter on a 512 MiB device-to-device copy), keyed by the SHA-256
+# of the kernel sources they were taken on; a changed kernel reports null.
+# Source: profiles/k_newton_118bus_b1024_hbm_counters.md
+MEASURED_TRAFFIC = {
+    "62931a784219604147770ceee49a50ea18b760bb6f1613ad2181c616bc718fb9": {"c1": 6654858},
+}
 
 
 def parse():
@@ -41,6 +51,15 @@ def parse():
                     help="run one device-to-device copy of this many MiB first, as the known-size "
                          "reference for HBM byte counters")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def algorithmic_bytes_per_solve(n_bus, nnz_lu, iters, w, refine):
@@ -197,7 +216,10 @@ def main():
                                             "n_levels_l", "n_levels_u", "lds_resident",
                                             "block_threads", "lds_bytes", "slice_width", "workspace_bytes")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(name)
+                                 if B == SPECS[name].batch else None),
+                     "kernel_source_sha256": kernel_source_hash()[:16],
                      "kernel": "k_newton<float> (mixed-precision Newton, one launch per solve)",
                      "bytes_per_launch": bytes_launch, "avg_launch_ms": 1e3 * tmp.mean()},
     }
