@@ -36,6 +36,8 @@ struct pf_template {
   double* ws_d = nullptr;
   void* ws_t = nullptr;
   int* ws_i = nullptr;
+  double* wsl_d = nullptr;   // HBM-resident slices of S > 1 scenarios
+  void* wsl_t = nullptr;
   size_t ws_bytes = 0;
   bool have_factors = false;
 };
@@ -156,6 +158,8 @@ sable::KParams base_params(const pf_template* t) {
   kp.ws_d = t->ws_d;
   kp.ws_t = t->ws_t;
   kp.ws_i = t->ws_i;
+  kp.wsl_d = t->wsl_d ? t->wsl_d : t->ws_d;
+  kp.wsl_t = t->wsl_t ? t->wsl_t : t->ws_t;
   kp.max_iter = t->opt.max_iter;
   kp.refine = t->fp32 ? t->opt.refine_steps : 0;
   kp.keep = t->opt.keep_factors;
@@ -307,26 +311,23 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     if (score > best_score) { best_score = score; best_s = sl; }
   }
   int nt = opt.block_threads;
-  t->wstride = round_up(4 * S.max_row_blocks, 8);
+  t->wstride = 0;
+  t->gmin = 4;
   if (best_s > 0) {
     t->lds_res = true;
     t->slice = best_s;
-    t->gmin = 4;
     t->lds_bytes = sable::kScratchBytes + (size_t)so.newton_bytes + best_s * per_scen;
     if (nt == 0) nt = 256;
   } else {
+    // HBM-resident: S scenarios interleaved per slice, S as large as keeps
+    // at least one slice per compute unit, one wavefront per scenario
     t->lds_res = false;
-    t->slice = 1;
-    if (nt == 0) nt = 256;
-    const size_t budget = std::min<size_t>(max_lds, 64 * 1024) - sable::kScratchBytes;
-    int g = 4;
-    while (g <= 64 && (size_t)(nt / g) * t->wstride * tsz > budget) g <<= 1;
-    if (g > 64) {
-      delete t;
-      return fail(PF_EINVAL, "pf_template_build: a factor row does not fit in LDS for this block size");
-    }
-    t->gmin = g;
-    t->lds_bytes = sable::kScratchBytes + (size_t)(nt / g) * t->wstride * tsz;
+    const int n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    int sl = 1;
+    while (sl < sable::kMaxSlice && batch / (2 * sl) >= n_cu) sl *= 2;
+    t->slice = sl;
+    t->lds_bytes = sable::kScratchBytes;
+    if (nt == 0) nt = std::min(1024, std::max(256, 64 * sl));
   }
   t->nt = nt;
 
@@ -343,11 +344,21 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     pf_template_destroy(t);
     return fail(PF_ENOMEM, "pf_template_build: device allocation (workspace)");
   }
+  size_t bsl = 0;
+  if (!t->lds_res && t->slice > 1) {
+    const size_t slices = (size_t)(batch + t->slice - 1) / t->slice;
+    const size_t sd = slices * t->slice * t->lay.sd * 8, stt = slices * t->slice * t->lay.st * tsz;
+    if (hipMalloc(&t->wsl_d, sd) != hipSuccess || hipMalloc(&t->wsl_t, stt) != hipSuccess) {
+      pf_template_destroy(t);
+      return fail(PF_ENOMEM, "pf_template_build: device allocation (slice workspace)");
+    }
+    bsl = sd + stt;
+  }
   he = hipMemset(t->ws_i, 0xff, bi);
   if (he == hipSuccess && t->lds_bytes > 64 * 1024) he = sable::set_lds_limits(t->lds_bytes);
   if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he != hipSuccess) { pf_template_destroy(t); return hip_fail(he, "pf_template_build: set-up"); }
-  t->ws_bytes = pk.buf.size() + bd + bt + bi;
+  t->ws_bytes = pk.buf.size() + bd + bt + bi + bsl;
   *out = t;
   return PF_OK;
 }
@@ -374,6 +385,8 @@ int pf_template_destroy(pf_template* t) {
   if (t->ws_d) (void)hipFree(t->ws_d);
   if (t->ws_t) (void)hipFree(t->ws_t);
   if (t->ws_i) (void)hipFree(t->ws_i);
+  if (t->wsl_d) (void)hipFree(t->wsl_d);
+  if (t->wsl_t) (void)hipFree(t->wsl_t);
   delete t;
   return PF_OK;
 }

@@ -18,13 +18,20 @@ enum Mode : int {
 };
 
 // LDS scratch at the start of every kernel's dynamic LDS: per-(wave,
-// scenario) partial maxima and flags, per-scenario zero-pivot flags.
+// scenario) partial maxima and flags, per-scenario reductions, zero-pivot
+// flags and Newton bookkeeping (iterations, status, final mismatch).
 constexpr int kMaxWaves = 16;
-constexpr int kMaxSlice = 8;
-constexpr int kRedOff = 0;                                     // double [16][8]
-constexpr int kFlagOff = kRedOff + 8 * kMaxWaves * kMaxSlice;  // int [16][8]
-constexpr int kPivOff = kFlagOff + 4 * kMaxWaves * kMaxSlice;  // int [8]
-constexpr int kScratchBytes = 2048;
+constexpr int kMaxSlice = 16;
+constexpr int kRedOff = 0;                                     // double [16][16]
+constexpr int kFlagOff = kRedOff + 8 * kMaxWaves * kMaxSlice;  // int [16][16]
+constexpr int kPivOff = kFlagOff + 4 * kMaxWaves * kMaxSlice;  // int [16]
+constexpr int kFnOff = kPivOff + 4 * kMaxSlice;                // double [16]
+constexpr int kBadOff = kFnOff + 8 * kMaxSlice;                // int [16]
+constexpr int kItOff = kBadOff + 4 * kMaxSlice;                // int [16]
+constexpr int kStOff = kItOff + 4 * kMaxSlice;                 // int [16]
+constexpr int kFnvOff = kStOff + 4 * kMaxSlice;                // double [16]
+constexpr int kScratchBytes = 4096;
+static_assert(kFnvOff + 8 * kMaxSlice <= kScratchBytes, "scratch layout");
 
 // Byte offsets of the symbolic arrays inside one packed image (device
 // memory; the prefix [0, newton_bytes) is what the Newton kernel reads and is
@@ -64,9 +71,11 @@ struct KParams {
   const unsigned char* sym;  // packed symbolic image (device)
   StateLayout lay;           // per-scenario layout of the HBM workspace
   StateLayout llay;          // per-scenario layout inside an LDS-resident slice
-  double* ws_d;
+  double* ws_d;              // per-scenario workspace (layout lay)
   void* ws_t;
   int* ws_i;
+  double* wsl_d;             // HBM-resident slices: S scenarios interleaved per slice
+  void* wsl_t;
   int mode, max_iter, refine, keep, count, gmin, wstride;
   double tol;
   const double *pd, *qd, *pg, *vset, *vm_in, *va_in, *rhs, *g_vm, *g_va;
@@ -74,7 +83,7 @@ struct KParams {
   int *iters_out, *status_out;
 };
 
-// slice = scenarios per workgroup (1, 2, 4 or 8); slice > 1 needs lds_res.
+// slice = scenarios per workgroup: 1, 2, 4 or 8 when LDS-resident, up to 16 otherwise.
 hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds,
                          bool lds_res, hipStream_t st);
 hipError_t launch_adjoint(const KParams& kp, bool fp32, int grid, int nt, hipStream_t st);

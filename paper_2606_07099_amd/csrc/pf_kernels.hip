@@ -180,10 +180,10 @@ __device__ __forceinline__ T group_sum(T v, int G) {
   return v;
 }
 
-// per-scenario max over the workgroup of v and OR of bad (thread's scenario
-// is tid % S); every thread receives all S results
+// per-scenario max over the workgroup of v and OR of bad (a thread's scenario
+// is tid % S); results land in the scratch arrays fn[S] / bad[S]
 template <int S>
-__device__ void block_max(double v, int bad, double* fn, int* bd, unsigned char* scr, int tid, int nt) {
+__device__ void block_max(double v, int bad, unsigned char* scr, int tid, int nt) {
   double* red = reinterpret_cast<double*>(scr + kRedOff);
   int* flg = reinterpret_cast<int*>(scr + kFlagOff);
   for (int o = 32; o >= S; o >>= 1) {
@@ -193,13 +193,12 @@ __device__ void block_max(double v, int bad, double* fn, int* bd, unsigned char*
   const int w = tid >> 6, l = tid & 63;
   if (l < S) { red[w * S + l] = v; flg[w * S + l] = bad; }
   __syncthreads();
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
+  if (tid < S) {
     double mx = 0.0;
     int b = 0;
-    for (int k = 0; k < (nt >> 6); ++k) { mx = fmax(mx, red[k * S + s]); b |= flg[k * S + s]; }
-    fn[s] = mx;
-    bd[s] = b;
+    for (int k = 0; k < (nt >> 6); ++k) { mx = fmax(mx, red[k * S + tid]); b |= flg[k * S + tid]; }
+    reinterpret_cast<double*>(scr + kFnOff)[tid] = mx;
+    reinterpret_cast<int*>(scr + kBadOff)[tid] = b;
   }
   __syncthreads();
 }
@@ -209,8 +208,8 @@ __device__ void block_max(double v, int bad, double* fn, int* bd, unsigned char*
 
 // I = Y V, S = V conj(I), F1 = spec - calc on the block rows; ||F1||_inf per scenario.
 template <typename T, int S>
-__device__ void phase_mismatch(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, double* fn,
-                               int* bd, unsigned char* scr) {
+__device__ void phase_mismatch(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
+                               unsigned char* scr) {
   double mx = 0.0;
   int bad = 0;
   const int s = tid % S;
@@ -240,7 +239,14 @@ __device__ void phase_mismatch(const Sym& m, const Dims& D, St<T>& c, int tid, i
     }
   }
   __syncthreads();
-  block_max<S>(mx, bad, fn, bd, scr, tid, nt);
+  block_max<S>(mx, bad, scr, tid, nt);
+}
+
+// orders this wavefront's earlier global stores before its later loads (HBM
+// state); LDS operations of a wavefront are already in order
+template <bool RES>
+__device__ __forceinline__ void wave_order() {
+  if (!RES) __threadfence_block();
 }
 
 // Jacobian values of every block of the pattern (fill-in blocks zeroed) for
@@ -266,8 +272,8 @@ __device__ void phase_fill(const Sym& m, const Dims& D, St<T>& c, int tid, int n
 // one lane writes in one step is seen by every lane in the next.  W is the
 // row: in place in an LDS-resident slice, a staging copy in LDS otherwise.
 template <typename T, int S, bool RES>
-__device__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, T* wsp, int tid, int nt,
-                             int gmin, int wstride, bool fwd, int* piv) {
+__device__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin,
+                             bool fwd, int* piv) {
   for (int lev = 0; lev < D.nlev_f; ++lev) {
     const int t0 = m.task_ptr[lev], t1 = m.task_ptr[lev + 1];
     const Grp g = groups(t1 - t0, tid, nt, gmin);
@@ -276,17 +282,11 @@ __device__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, T* wsp, int 
       const int4 tk = m.task4[ti];
       const int a = tk.x;
       const int rs = m.rp[a];
-      T* W;
-      if (RES) {
-        W = c.lu + sB<S>(rs, 0);
-      } else {
-        W = wsp + (size_t)g.gid * wstride;
-        const int len = m.rp[a + 1] - rs;
-        for (int q = e; q < len; q += E) st_blk(W + sB<S>(q, s), ld_blk(c.lu + sB<S>(rs + q, s)));
-      }
+      T* W = c.lu + sB<S>(rs, 0);
       T y0 = T(0), y1 = T(0);
       if (fwd) { y0 = c.y[sP<S>(a, s)]; y1 = c.y[sP<S>(a, s) + 1]; }
       for (int i = tk.y; i < tk.z; ++i) {
+        if (i > tk.y) wave_order<RES>();   // the previous step's targets may feed this one
         const int4 st = m.step4[i];   // q, k, start of U(k,>k), |U(k,>k)|
         const int ts = m.step_ts[i];
         const int k = st.y;
@@ -308,23 +308,21 @@ __device__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, T* wsp, int 
       }
       if (e == 0) {
         if (tk.w) {
+          if (tk.z - tk.y > 1) wave_order<RES>();
           const Blk<T> Dk = ld_blk(W + sB<S>(m.diag[a] - rs, s));
           const T det = Dk.a * Dk.d - Dk.b * Dk.c;
           const T inv = T(1) / det;
           const Blk<T> Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
           // pivots of the block: a, then the Schur complement d - c b / a
-          const T p1 = Dk.a, p2 = det / Dk.a;
+          // (|det / a| > eps (|c| + |d|) written without the division)
           const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
-          const bool zero = !(fabs(p1) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
-                            !(fabs(p2) > eps * (fabs(Dk.c) + fabs(Dk.d))) || !isfinite(inv);
+          const bool zero = !(fabs(Dk.a) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
+                            !(fabs(det) > eps * fabs(Dk.a) * (fabs(Dk.c) + fabs(Dk.d))) ||
+                            !isfinite(inv);
           if (zero) piv[s] = 1;
           st_blk(c.dinv + sB<S>(a, s), Di);
         }
         if (fwd) { c.y[sP<S>(a, s)] = y0; c.y[sP<S>(a, s) + 1] = y1; }
-      }
-      if (!RES) {
-        const int len = m.rp[a + 1] - rs;
-        for (int q = e; q < len; q += E) st_blk(c.lu + sB<S>(rs + q, s), ld_blk(W + sB<S>(q, s)));
       }
     }
     __syncthreads();
@@ -459,13 +457,6 @@ __device__ __forceinline__ float lane_bcast(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// orders this wavefront's earlier global stores before its later loads (HBM
-// state); LDS operations of a wavefront are already in order
-template <bool RES>
-__device__ __forceinline__ void wave_order() {
-  if (!RES) __threadfence_block();
-}
-
 // LU of the tail rows, one pivot at a time in row order: the pivot block is
 // inverted, then every tail row with a multiplier for this pivot forms it,
 // applies it to its right-hand side entry and to its targets of the pivot's
@@ -487,10 +478,10 @@ __device__ void phase_tail_factor(const Sym& m, const Dims& D, St<T>& c, int tid
         const T inv = T(1) / det;
         Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
         // pivots of the block: a, then the Schur complement d - c b / a
-        const T p1 = Dk.a, p2 = det / Dk.a;
         const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
-        const bool zero = !(fabs(p1) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
-                          !(fabs(p2) > eps * (fabs(Dk.c) + fabs(Dk.d))) || !isfinite(inv);
+        const bool zero = !(fabs(Dk.a) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
+                          !(fabs(det) > eps * fabs(Dk.a) * (fabs(Dk.c) + fabs(Dk.d))) ||
+                          !isfinite(inv);
         if (zero) piv[s] = 1;
         st_blk(c.dinv + sB<S>(ak, s), Di);
       }
@@ -717,6 +708,11 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
   const Dims& D = kp.dims;
   unsigned char* scr = smem;
   int* piv = reinterpret_cast<int*>(scr + kPivOff);
+  const double* fnr = reinterpret_cast<const double*>(scr + kFnOff);
+  const int* bdr = reinterpret_cast<const int*>(scr + kBadOff);
+  int* s_it = reinterpret_cast<int*>(scr + kItOff);
+  int* s_st = reinterpret_cast<int*>(scr + kStOff);
+  double* s_fn = reinterpret_cast<double*>(scr + kFnvOff);
 
   const unsigned char* mbase = kp.sym;
   if (RES) {   // the shared symbolic image, once per workgroup, 16 bytes per lane
@@ -727,23 +723,19 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
   }
   const Sym m = bind_sym(mbase, kp.sym, kp.so);
   St<T> c;
-  T* wsp = nullptr;
   if (RES) {
     double* d = reinterpret_cast<double*>(smem + kScratchBytes + kp.so.newton_bytes);
     c = bind_state<T, S>(d, reinterpret_cast<T*>(d + (size_t)kp.llay.sd * S), kp.llay);
   } else {
-    c = bind_state<T, 1>(kp.ws_d + (size_t)slice * kp.lay.sd,
-                         reinterpret_cast<T*>(kp.ws_t) + (size_t)slice * kp.lay.st, kp.lay);
-    wsp = reinterpret_cast<T*>(smem + kScratchBytes);
+    c = bind_state<T, S>(kp.wsl_d + (size_t)slice * S * kp.lay.sd,
+                         reinterpret_cast<T*>(kp.wsl_t) + (size_t)slice * S * kp.lay.st, kp.lay);
   }
-  if (tid < S) piv[tid] = 0;
+  if (tid < S) { piv[tid] = 0; s_it[tid] = 0; s_st[tid] = 0; s_fn[tid] = 0.0; }
 
   const int n = D.n_bus, nb = D.nb;
   int act = 0;   // scenarios of the slice still iterating (identical in every thread)
-#pragma unroll
   for (int s = 0; s < S; ++s)
     if (slice * S + s < kp.count) act |= 1 << s;
-  const int valid = act;
 
   // inputs: specified injections and the start point; padding scenarios of
   // the last slice get an empty problem and are never written back
@@ -773,36 +765,35 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
   __syncthreads();
   phase_set_state<T, S>(D, c, tid, nt, (1 << S) - 1);
 
-  int iters[S], status[S];
-  double fnv[S];
-#pragma unroll
-  for (int s = 0; s < S; ++s) { iters[s] = 0; status[s] = 0; fnv[s] = 0.0; }
   const bool mixed = sizeof(T) == 4;
-  const int gmin = RES ? (kp.gmin > S ? kp.gmin : S) : kp.gmin;
+  const int gmin = kp.gmin > S ? kp.gmin : S;
   while (true) {
-    double fn[S];
-    int bad[S];
-    phase_mismatch<T, S>(m, D, c, tid, nt, fn, bad, scr);
-#pragma unroll
+    phase_mismatch<T, S>(m, D, c, tid, nt, scr);
     for (int s = 0; s < S; ++s) {
       if (!((act >> s) & 1)) continue;
-      fnv[s] = fn[s];
-      if (bad[s]) { status[s] = 2; act &= ~(1 << s); continue; }
-      if (kp.mode == MODE_SOLVE) {
-        if (fn[s] < kp.tol) { status[s] = 0; act &= ~(1 << s); }
-        else if (iters[s] >= kp.max_iter) { status[s] = 1; act &= ~(1 << s); }
+      const double f = fnr[s];
+      int st = -1;
+      if (bdr[s]) st = 2;
+      else if (kp.mode == MODE_SOLVE && f < kp.tol) st = 0;
+      else if (kp.mode == MODE_SOLVE && s_it[s] >= kp.max_iter) st = 1;
+      if (tid == 0) s_fn[s] = f;
+      if (st >= 0) {
+        act &= ~(1 << s);
+        if (tid == 0) s_st[s] = st;
       }
     }
     if (kp.mode == MODE_EVAL_MISMATCH || kp.mode == MODE_EVAL_FACTOR) break;
     if (!act) break;
     for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
     phase_fill<T, S>(m, D, c, tid, nt);
-    phase_factor<T, S, RES>(m, D, c, wsp, tid, nt, gmin, kp.wstride, true, piv);
+    phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, true, piv);
     phase_tail_factor<T, S, RES>(m, D, c, tid, nt, true, piv);
     __syncthreads();
-#pragma unroll
     for (int s = 0; s < S; ++s)
-      if (((act >> s) & 1) && piv[s]) { status[s] = 3; act &= ~(1 << s); }
+      if (((act >> s) & 1) && piv[s]) {
+        act &= ~(1 << s);
+        if (tid == 0) s_st[s] = 3;
+      }
     if (!act) break;
     phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
     __syncthreads();
@@ -835,10 +826,9 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
     }
     __syncthreads();
     phase_set_state<T, S>(D, c, tid, nt, act);
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-      if ((act >> s) & 1) iters[s]++;
+    if (tid < S && ((act >> tid) & 1)) s_it[tid]++;
   }
+  __syncthreads();
 
   // outputs
   if (kp.mode == MODE_SOLVE) {
@@ -850,14 +840,11 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
         kp.va_out[(size_t)b * n + i] = c.va[idx];
       }
     }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int b = slice * S + s;
-      if (tid == s && b < kp.count) {
-        if (kp.iters_out) kp.iters_out[b] = iters[s];
-        if (kp.status_out) kp.status_out[b] = status[s];
-        if (kp.fnorm_out) kp.fnorm_out[b] = status[s] == 2 ? __builtin_nan("") : fnv[s];
-      }
+    if (tid < S && slice * S + tid < kp.count) {
+      const int b = slice * S + tid;
+      if (kp.iters_out) kp.iters_out[b] = s_it[tid];
+      if (kp.status_out) kp.status_out[b] = s_st[tid];
+      if (kp.fnorm_out) kp.fnorm_out[b] = s_st[tid] == 2 ? __builtin_nan("") : s_fn[tid];
     }
   } else if (kp.mode == MODE_EVAL_MISMATCH || kp.mode == MODE_EVAL_STEP) {
     const int nj = D.nj;
@@ -879,16 +866,13 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
   // keep the converged state and the factors of J1 at it for the adjoint
   const bool keep = (kp.mode == MODE_SOLVE && kp.keep) || kp.mode == MODE_EVAL_FACTOR;
   if (keep) {
-    __syncthreads();
     if (tid < S) piv[tid] = 0;
     phase_fill<T, S>(m, D, c, tid, nt);
-    phase_factor<T, S, RES>(m, D, c, wsp, tid, nt, gmin, kp.wstride, false, piv);
+    phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, false, piv);
     phase_tail_factor<T, S, RES>(m, D, c, tid, nt, false, piv);
     __syncthreads();
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-      if (status[s] == 0 && piv[s]) status[s] = 3;
-    if (RES) {   // scatter the slice into the per-scenario HBM workspace
+    if (tid < S && s_st[tid] == 0 && piv[tid]) s_st[tid] = 3;
+    if (RES || S > 1) {   // scatter the slice into the per-scenario workspace
       for (int s = 0; s < S; ++s) {
         const int b = slice * S + s;
         if (b >= kp.count) break;
@@ -904,17 +888,13 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
         }
       }
     }
+    __syncthreads();
   }
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int b = slice * S + s;
-    if (tid == s && b < kp.count) {
-      int* gi = kp.ws_i + (size_t)b * 4;
-      gi[0] = keep ? status[s] : -1;
-      gi[1] = iters[s];
-    }
+  if (tid < S && slice * S + tid < kp.count) {
+    int* gi = kp.ws_i + (size_t)(slice * S + tid) * 4;
+    gi[0] = keep ? s_st[tid] : -1;
+    gi[1] = s_it[tid];
   }
-  (void)valid;
 }
 
 // ----------------------------------------------------------------------------
@@ -1072,7 +1052,14 @@ static hipError_t launch_newton_t(const KParams& kp, int slice, int grid, int nt
                                   bool res, hipStream_t st) {
   dim3 g(grid), b(nt);
   if (!res) {
-    hipLaunchKernelGGL((k_newton<T, false, 1>), g, b, lds, st, kp);
+    switch (slice) {
+      case 1: hipLaunchKernelGGL((k_newton<T, false, 1>), g, b, lds, st, kp); break;
+      case 2: hipLaunchKernelGGL((k_newton<T, false, 2>), g, b, lds, st, kp); break;
+      case 4: hipLaunchKernelGGL((k_newton<T, false, 4>), g, b, lds, st, kp); break;
+      case 8: hipLaunchKernelGGL((k_newton<T, false, 8>), g, b, lds, st, kp); break;
+      case 16: hipLaunchKernelGGL((k_newton<T, false, 16>), g, b, lds, st, kp); break;
+      default: return hipErrorInvalidValue;
+    }
   } else {
     switch (slice) {
       case 1: hipLaunchKernelGGL((k_newton<T, true, 1>), g, b, lds, st, kp); break;
@@ -1113,6 +1100,10 @@ static hipError_t set_lds_t(int max_lds) {
     if (r != hipSuccess) e = r;
   };
   set(reinterpret_cast<const void*>(&k_newton<T, false, 1>));
+  set(reinterpret_cast<const void*>(&k_newton<T, false, 2>));
+  set(reinterpret_cast<const void*>(&k_newton<T, false, 4>));
+  set(reinterpret_cast<const void*>(&k_newton<T, false, 8>));
+  set(reinterpret_cast<const void*>(&k_newton<T, false, 16>));
   set(reinterpret_cast<const void*>(&k_newton<T, true, 1>));
   set(reinterpret_cast<const void*>(&k_newton<T, true, 2>));
   set(reinterpret_cast<const void*>(&k_newton<T, true, 4>));
