@@ -84,7 +84,9 @@ typedef struct {
                             default 2; ignored for PF_FP64 */
   int32_t keep_factors;  /* 1 (default): after convergence re-evaluate J1 and refactor
                             at the solution and keep the factors for pf_adjoint_batch */
-  int32_t block_threads; /* threads per workgroup, 0 = automatic (64..1024) */
+  int32_t block_threads; /* threads per workgroup, 0 = automatic (64..1024); LDS-resident
+                            slices always run 256 threads, so any other nonzero value
+                            selects HBM-resident slices */
 } pf_options;
 
 typedef struct {

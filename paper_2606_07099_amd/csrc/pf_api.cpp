@@ -242,7 +242,10 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   pf_template* t = new (std::nothrow) pf_template();
   if (!t) return fail(PF_ENOMEM, "pf_template_build: host allocation failed");
   std::string err;
-  int rc = sable::analyze(n_bus, bus_type, y_indptr, y_indices, y_g, y_b, t->sym, err);
+  // the dense tail of an LDS-resident slice lives in registers: at most 32
+  // block rows in FP32, 16 in FP64
+  const int tail_max = opt.precision == PF_MIXED ? 32 : 16;
+  int rc = sable::analyze(n_bus, bus_type, y_indptr, y_indices, y_g, y_b, t->sym, err, tail_max);
   if (rc != PF_OK) { delete t; return fail(rc, err); }
   if (!structurally_symmetric(t->sym)) {
     delete t;
@@ -282,6 +285,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   so.lev_um_ptr = (int)pk.add(S.lev_um_ptr); so.lev_um_rows = (int)pk.add(S.lev_um_rows);
   so.tail_pos = (int)pk.add(S.tail_pos); so.tail_split = (int)pk.add(S.tail_split);
   so.tk_ptr = (int)pk.add(S.tk_ptr); so.tstep4 = (int)pk.add(S.tstep4);
+  so.tail_mask = (int)pk.add(S.tail_mask);
   so.newton_bytes = (int)pk.align();
   so.lev_u_ptr = (int)pk.add(S.lev_u_ptr); so.lev_u_rows = (int)pk.add(S.lev_u_rows);
   so.blk_bus = (int)pk.add(S.blk_bus); so.lu_src = (int)pk.add(S.lu_src);
@@ -295,16 +299,19 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   dm.nlev_bs = (int)S.lev_um_ptr.size() - 1;
   dm.tail_t = S.tail_t; dm.tail_base = S.tail_base;
 
-  // ---- launch shape: LDS-resident slices of S scenarios when they fit,
+  // ---- launch shape: LDS-resident slices of S <= 4 scenarios (256 threads,
+  // one wavefront per scenario's register-resident tail) when they fit,
   // choosing S to maximise the scenarios resident per CU; HBM-resident
-  // single-scenario workgroups otherwise
+  // slices of up to 16 scenarios otherwise
   t->lay = make_layout(S.n_bus, S.nb, S.nnzb());
   t->llay = make_lds_layout(S.n_bus, S.nb, S.nnzb(), t->fp32);
   const size_t lds_cu = std::max<size_t>(max_lds, (size_t)prop.maxSharedMemoryPerMultiProcessor);
   const size_t per_scen = 8 * (size_t)t->llay.sd + tsz * (size_t)t->llay.st;
   int best_s = 0;
   size_t best_score = 0;
-  for (int sl : {8, 4, 2, 1}) {
+  const bool res_ok = opt.block_threads == 0 || opt.block_threads == sable::kResThreads;
+  for (int sl : {4, 2, 1}) {
+    if (!res_ok || sl > sable::kResMaxSlice) continue;
     const size_t need = sable::kScratchBytes + (size_t)so.newton_bytes + sl * per_scen;
     if (need > max_lds) continue;
     const size_t score = (lds_cu / need) * sl;
@@ -317,7 +324,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     t->lds_res = true;
     t->slice = best_s;
     t->lds_bytes = sable::kScratchBytes + (size_t)so.newton_bytes + best_s * per_scen;
-    if (nt == 0) nt = 256;
+    nt = sable::kResThreads;
   } else {
     // HBM-resident: S scenarios interleaved per slice, S as large as keeps
     // at least one slice per compute unit, one wavefront per scenario

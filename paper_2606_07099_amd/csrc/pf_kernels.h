@@ -40,6 +40,7 @@ struct SymOffsets {
   int bus_type, bus_blk, y_rp, y_ci, y_g, y_b;
   int rp, ci, diag, fill4, task_ptr, task4, step4, step_ts, upd_tgt;
   int lev_l_ptr, lev_l_rows, lev_um_ptr, lev_um_rows, tail_pos, tail_split, tk_ptr, tstep4;
+  int tail_mask;
   int newton_bytes;
   int lev_u_ptr, lev_u_rows;
   int blk_bus, lu_src, mirror, y_tr, ord_p, ord_q;
@@ -83,7 +84,12 @@ struct KParams {
   int *iters_out, *status_out;
 };
 
-// slice = scenarios per workgroup: 1, 2, 4 or 8 when LDS-resident, up to 16 otherwise.
+// LDS-resident slices: one wavefront per scenario for the register-resident
+// dense tail, 256 threads, at most 4 scenarios per workgroup
+constexpr int kResThreads = 256;
+constexpr int kResMaxSlice = 4;
+
+// slice = scenarios per workgroup: 1, 2 or 4 when LDS-resident, up to 16 otherwise.
 hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds,
                          bool lds_res, hipStream_t st);
 hipError_t launch_adjoint(const KParams& kp, bool fp32, int grid, int nt, hipStream_t st);

@@ -54,6 +54,7 @@ struct Sym {
   const int *lev_l_ptr, *lev_l_rows, *lev_u_ptr, *lev_u_rows;
   const int *lev_um_ptr, *lev_um_rows, *tail_pos, *tail_split, *tk_ptr;
   const int4* tstep4;
+  const unsigned* tail_mask;
   const int *blk_bus, *lu_src, *mirror, *y_tr, *ord_p, *ord_q;
 };
 
@@ -83,6 +84,7 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
   m.tail_split = reinterpret_cast<const int*>(nb + o.tail_split);
   m.tk_ptr = reinterpret_cast<const int*>(nb + o.tk_ptr);
   m.tstep4 = reinterpret_cast<const int4*>(nb + o.tstep4);
+  m.tail_mask = reinterpret_cast<const unsigned*>(nb + o.tail_mask);
   m.lev_u_ptr = reinterpret_cast<const int*>(g + o.lev_u_ptr);
   m.lev_u_rows = reinterpret_cast<const int*>(g + o.lev_u_rows);
   m.blk_bus = reinterpret_cast<const int*>(g + o.blk_bus);
@@ -183,7 +185,7 @@ __device__ __forceinline__ T group_sum(T v, int G) {
 // per-scenario max over the workgroup of v and OR of bad (a thread's scenario
 // is tid % S); results land in the scratch arrays fn[S] / bad[S]
 template <int S>
-__device__ void block_max(double v, int bad, unsigned char* scr, int tid, int nt) {
+__device__ __forceinline__ void block_max(double v, int bad, unsigned char* scr, int tid, int nt) {
   double* red = reinterpret_cast<double*>(scr + kRedOff);
   int* flg = reinterpret_cast<int*>(scr + kFlagOff);
   for (int o = 32; o >= S; o >>= 1) {
@@ -208,7 +210,7 @@ __device__ void block_max(double v, int bad, unsigned char* scr, int tid, int nt
 
 // I = Y V, S = V conj(I), F1 = spec - calc on the block rows; ||F1||_inf per scenario.
 template <typename T, int S>
-__device__ void phase_mismatch(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
+__device__ __forceinline__ void phase_mismatch(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
                                unsigned char* scr) {
   double mx = 0.0;
   int bad = 0;
@@ -252,7 +254,7 @@ __device__ __forceinline__ void wave_order() {
 // Jacobian values of every block of the pattern (fill-in blocks zeroed) for
 // the S scenarios: independent work, one pass before the factorisation.
 template <typename T, int S>
-__device__ void phase_fill(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+__device__ __forceinline__ void phase_fill(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
   for (int idx = tid; idx < D.nnzb * S; idx += nt) {
     const int p = idx / S, s = idx % S;
     st_blk(c.lu + sB<S>(p, s), fill_block<T, S>(m, c, p, s));
@@ -272,7 +274,7 @@ __device__ void phase_fill(const Sym& m, const Dims& D, St<T>& c, int tid, int n
 // one lane writes in one step is seen by every lane in the next.  W is the
 // row: in place in an LDS-resident slice, a staging copy in LDS otherwise.
 template <typename T, int S, bool RES>
-__device__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin,
+__device__ __forceinline__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin,
                              bool fwd, int* piv) {
   for (int lev = 0; lev < D.nlev_f; ++lev) {
     const int t0 = m.task_ptr[lev], t1 = m.task_ptr[lev + 1];
@@ -331,7 +333,7 @@ __device__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, int tid, int
 
 // L y = y (unit block-lower, in place) by L-levels
 template <typename T, int S>
-__device__ void phase_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
+__device__ __forceinline__ void phase_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
   for (int lev = 0; lev < D.nlev_fs; ++lev) {
     const int r0 = m.lev_l_ptr[lev], r1 = m.lev_l_ptr[lev + 1];
     const Grp g = groups(r1 - r0, tid, nt, gmin);
@@ -358,7 +360,7 @@ __device__ void phase_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int
 // U x = y (block-upper with full diagonal blocks, in place) by U-levels, for
 // the rows outside the dense tail (whose unknowns are solved first)
 template <typename T, int S>
-__device__ void phase_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
+__device__ __forceinline__ void phase_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
   for (int lev = 0; lev < D.nlev_bs; ++lev) {
     const int r0 = m.lev_um_ptr[lev], r1 = m.lev_um_ptr[lev + 1];
     const Grp g = groups(r1 - r0, tid, nt, gmin);
@@ -389,7 +391,7 @@ __device__ void phase_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int
 
 // U^T w = g (in place in y) by L-levels: w_a = U_aa^-T (g_a - sum_k U_ka^T w_k)
 template <typename T>
-__device__ void phase_ut_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
+__device__ __forceinline__ void phase_ut_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
   for (int lev = 0; lev < D.nlev_l; ++lev) {
     const int r0 = m.lev_l_ptr[lev], r1 = m.lev_l_ptr[lev + 1];
     const Grp g = groups(r1 - r0, tid, nt, gmin);
@@ -419,7 +421,7 @@ __device__ void phase_ut_solve(const Sym& m, const Dims& D, St<T>& c, int tid, i
 
 // L^T l = w (in place in y) by U-levels: l_a = w_a - sum_j L_ja^T l_j
 template <typename T>
-__device__ void phase_lt_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
+__device__ __forceinline__ void phase_lt_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
   for (int lev = 0; lev < D.nlev_u; ++lev) {
     const int r0 = m.lev_u_ptr[lev], r1 = m.lev_u_ptr[lev + 1];
     const Grp g = groups(r1 - r0, tid, nt, gmin);
@@ -463,7 +465,7 @@ __device__ __forceinline__ float lane_bcast(float v, int l) {
 // U row, lanes = (elimination step, entry of the U row).  Same arithmetic as
 // the barrier-synchronised tasks, one pivot per wavefront step.
 template <typename T, int S, bool RES>
-__device__ void phase_tail_factor(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, bool fwd,
+__device__ __forceinline__ void phase_tail_factor(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, bool fwd,
                                   int* piv) {
   const int t = D.tail_t, tb = D.tail_base;
   const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
@@ -526,7 +528,7 @@ __device__ void phase_tail_factor(const Sym& m, const Dims& D, St<T>& c, int tid
 // forward solve of the tail rows: their terms on rows outside the tail,
 // then the unit block-lower tail block, broadcasting each finished unknown
 template <typename T, int S, bool RES>
-__device__ void phase_tail_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+__device__ __forceinline__ void phase_tail_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
   const int t = D.tail_t, tb = D.tail_base;
   const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
   for (int s = w; s < S; s += nw) {
@@ -561,7 +563,7 @@ __device__ void phase_tail_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid
 // backward solve of the tail block (its rows only couple to tail columns):
 // the last unknown first, each finished one broadcast to the rows above
 template <typename T, int S, bool RES>
-__device__ void phase_tail_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+__device__ __forceinline__ void phase_tail_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
   const int t = D.tail_t, tb = D.tail_base;
   const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
   for (int s = w; s < S; s += nw) {
@@ -588,9 +590,206 @@ __device__ void phase_tail_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid
   }
 }
 
+// ----------------------------------------------------------------------------
+// register-resident dense tail (LDS-resident slices): wavefront w handles the
+// tail of scenario w, lane l < t holds tail row l as 2x2 blocks in registers
+// for the duration of one tail phase (L part left of the diagonal, the
+// inverted pivot block on it, U part right of it).  The row is a register
+// vector per block component, indexed with the wavefront-uniform column
+// (register-indexing mode, no scratch); pivot rows and solved unknowns reach
+// the other lanes by lane broadcast; the structure masks skip the updates of
+// structurally zero blocks.  Same arithmetic, in the same order, as the
+// sparse per-pivot elimination.
+
+// register capacity of the dense tail, in block rows (one 32-dword register
+// tuple per block component)
+template <typename T>
+constexpr int tail_cap() { return sizeof(T) == 4 ? 32 : 16; }
+
+template <typename T>
+struct TailRow {
+  typedef T V __attribute__((ext_vector_type(tail_cap<T>())));
+  V a, b, c, d;
+  __device__ __forceinline__ Blk<T> get(int j) const { return {a[j], b[j], c[j], d[j]}; }
+  __device__ __forceinline__ void set(int j, const Blk<T>& x) { a[j] = x.a; b[j] = x.b; c[j] = x.c; d[j] = x.d; }
+};
+
+template <typename T>
+__device__ __forceinline__ Blk<T> bcast_blk(const Blk<T>& x, int l) {
+  return {lane_bcast(x.a, l), lane_bcast(x.b, l), lane_bcast(x.c, l), lane_bcast(x.d, l)};
+}
+
+template <typename T>
+__device__ __forceinline__ Blk<T> sel_blk(bool p, const Blk<T>& x, const Blk<T>& y) {
+  return {p ? x.a : y.a, p ? x.b : y.b, p ? x.c : y.c, p ? x.d : y.d};
+}
+
+// blocks (l, j) of the tail for j in [j0, j1) into R (zero elsewhere); the
+// pivot block (l, l) comes from the inverted pivots when inv_diag
+template <typename T, int S>
+__device__ __forceinline__ void rt_load(const Sym& m, const Dims& D, const St<T>& c, int s, int l,
+                                        int j0, int j1, bool inv_diag, TailRow<T>& R) {
+  R = TailRow<T>{};
+  const int t = D.tail_t, tb = D.tail_base;
+  const Blk<T> z = {T(0), T(0), T(0), T(0)};
+  // eight columns at a time, their index and value loads issued together
+  for (int jb = 0; jb < t; jb += 8) {
+    int p[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = jb + u;
+      p[u] = -1;
+      if (j < t && l < t && j >= j0 && j < j1) p[u] = (inv_diag && j == l) ? -2 : m.tail_pos[l * t + j];
+    }
+    Blk<T> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      v[u] = z;
+      if (p[u] == -2) v[u] = ld_blk(c.dinv + sB<S>(tb + l, s));
+      else if (p[u] >= 0) v[u] = ld_blk(c.lu + sB<S>(p[u], s));
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (jb + u < t) R.set(jb + u, v[u]);
+  }
+}
+
+// LU of the tail rows pivot by pivot, kept in R for the tail solves of the
+// iteration; with fwd, the forward solve of the tail rows' right-hand sides
+// is fused in
+template <typename T, int S>
+__device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c, int s, int l, bool fwd,
+                                          int* piv, TailRow<T>& R) {
+  const int t = D.tail_t, tb = D.tail_base;
+  if (t == 0) return;
+  rt_load<T, S>(m, D, c, s, l, 0, t, false, R);
+  T y0 = T(0), y1 = T(0);
+  if (fwd && l < t) { y0 = c.y[sP<S>(tb + l, s)]; y1 = c.y[sP<S>(tb + l, s) + 1]; }
+  bool zero = false;
+  for (int k = 0; k < t; ++k) {
+    const Blk<T> Ak = R.get(k);
+    const Blk<T> Dk = bcast_blk(Ak, k);
+    const T det = Dk.a * Dk.d - Dk.b * Dk.c;
+    const T inv = T(1) / det;
+    const Blk<T> Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
+    // pivots of the block: a, then the Schur complement d - c b / a
+    const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
+    zero |= !(fabs(Dk.a) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
+            !(fabs(det) > eps * fabs(Dk.a) * (fabs(Dk.c) + fabs(Dk.d))) || !isfinite(inv);
+    const bool below = l > k && l < t;
+    const Blk<T> L = mul(Ak, Di);
+    R.set(k, sel_blk(below, L, sel_blk(l == k, Di, Ak)));
+    if (fwd) {
+      const T yk0 = lane_bcast(y0, k), yk1 = lane_bcast(y1, k);
+      if (below) {
+        y0 -= L.a * yk0 + L.b * yk1;
+        y1 -= L.c * yk0 + L.d * yk1;
+      }
+    }
+    unsigned mk = __builtin_amdgcn_readfirstlane(m.tail_mask[k]);
+    while (mk) {
+      const int j = __builtin_ctz(mk);
+      mk &= mk - 1;
+      const Blk<T> X = R.get(j);
+      const Blk<T> U = bcast_blk(X, k);
+      const Blk<T> LU = mul(L, U);
+      const Blk<T> Y = {X.a - LU.a, X.b - LU.b, X.c - LU.c, X.d - LU.d};
+      R.set(j, sel_blk(below, Y, X));
+    }
+  }
+  if (zero && l == 0) piv[s] = 1;
+  if (fwd && l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+}
+
+// the tail factors back into the slice's storage (multipliers and U blocks
+// in place, inverted pivots to dinv), for the adjoint
+template <typename T, int S>
+__device__ __forceinline__ void rt_store(const Sym& m, const Dims& D, St<T>& c, int s, int l,
+                                         const TailRow<T>& R) {
+  const int t = D.tail_t, tb = D.tail_base;
+  for (int jb = 0; jb < t; jb += 8) {
+    int p[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = jb + u;
+      p[u] = -1;
+      if (j < t && l < t) p[u] = j == l ? -2 : m.tail_pos[l * t + j];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (jb + u < t) {
+        const Blk<T> X = R.get(jb + u);
+        if (p[u] == -2) st_blk(c.dinv + sB<S>(tb + l, s), X);
+        else if (p[u] >= 0) st_blk(c.lu + sB<S>(p[u], s), X);
+      }
+    }
+  }
+}
+
+// forward solve of the tail rows: their terms on rows outside the tail,
+// then the unit block-lower tail block
+template <typename T, int S>
+__device__ __forceinline__ void rt_fsolve(const Sym& m, const Dims& D, St<T>& c, int s, int l,
+                                          const TailRow<T>& R) {
+  const int t = D.tail_t, tb = D.tail_base;
+  if (t == 0) return;
+  T y0 = T(0), y1 = T(0);
+  if (l < t) {
+    const int a = tb + l;
+    y0 = c.y[sP<S>(a, s)];
+    y1 = c.y[sP<S>(a, s) + 1];
+    for (int p = m.rp[a]; p < m.tail_split[l]; ++p) {
+      const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
+      const int k = m.ci[p];
+      const T z0 = c.y[sP<S>(k, s)], z1 = c.y[sP<S>(k, s) + 1];
+      y0 -= L.a * z0 + L.b * z1;
+      y1 -= L.c * z0 + L.d * z1;
+    }
+  }
+  unsigned lm = __builtin_amdgcn_readfirstlane(m.tail_mask[t]);
+  while (lm) {
+    const int j = __builtin_ctz(lm);
+    lm &= lm - 1;
+    const Blk<T> L = R.get(j);
+    const T yj0 = lane_bcast(y0, j), yj1 = lane_bcast(y1, j);
+    if (l > j && l < t) {
+      y0 -= L.a * yj0 + L.b * yj1;
+      y1 -= L.c * yj0 + L.d * yj1;
+    }
+  }
+  if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+}
+
+// backward solve of the tail block, the last unknown first
+template <typename T, int S>
+__device__ __forceinline__ void rt_bsolve(const Sym& m, const Dims& D, St<T>& c, int s, int l,
+                                          const TailRow<T>& R) {
+  const int t = D.tail_t, tb = D.tail_base;
+  if (t == 0) return;
+  T y0 = T(0), y1 = T(0);
+  if (l < t) { y0 = c.y[sP<S>(tb + l, s)]; y1 = c.y[sP<S>(tb + l, s) + 1]; }
+  const unsigned cm = __builtin_amdgcn_readfirstlane(m.tail_mask[t + 1]);
+  for (int j = t - 1; j >= 0; --j) {
+    const Blk<T> X = R.get(j);
+    if (l == j) {
+      const T x0 = X.a * y0 + X.b * y1, x1 = X.c * y0 + X.d * y1;
+      y0 = x0;
+      y1 = x1;
+    }
+    if ((cm >> j) & 1u) {
+      const T xj0 = lane_bcast(y0, j), xj1 = lane_bcast(y1, j);
+      if (l < j) {
+        y0 -= X.a * xj0 + X.b * xj1;
+        y1 -= X.c * xj0 + X.d * xj1;
+      }
+    }
+  }
+  if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+}
+
 // dV = V (d|V|/|V| + j dtheta) for the correction dx (slack: 0)
 template <typename T, int S>
-__device__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+__device__ __forceinline__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
   for (int idx = tid; idx < D.n_bus * S; idx += nt) {
     const int i = idx / S, s = idx % S;
     const int a = m.bus_blk[i];
@@ -610,7 +809,7 @@ __device__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, int tid, int nt)
 // r = -F1 - J1 dx in FP64 without forming J1: J1 dx = -(dS restricted to the
 // F1 rows), dS = dV conj(I) + V conj(Y dV).  Result cast into y.
 template <typename T, int S>
-__device__ void phase_residual(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+__device__ __forceinline__ void phase_residual(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
   for (int idx = tid; idx < D.n_bus * S; idx += nt) {
     const int i = idx / S, s = idx % S;
     const int a = m.bus_blk[i];
@@ -644,7 +843,7 @@ __device__ void phase_residual(const Sym& m, const Dims& D, St<T>& c, int tid, i
 // Also stores Re(V_m c_m) / |V_m| = -(J3^T lam)_m for every bus in aux.
 // g == nullptr: only aux is produced.  One scenario (HBM state).
 template <typename T>
-__device__ void phase_adj_residual(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
+__device__ __forceinline__ void phase_adj_residual(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
                                    const double* lam, const double* g, bool to_y) {
   for (int i = tid; i < D.n_bus; i += nt) {   // w_i = nu_i conj(V_i) -> (dvr, dvi)
     const int a = m.bus_blk[i];
@@ -686,7 +885,7 @@ __device__ void phase_adj_residual(const Sym& m, const Dims& D, St<T>& c, int ti
 
 // e + jf from (|V|, theta) for the scenarios in `mask`
 template <typename T, int S>
-__device__ void phase_set_state(const Dims& D, St<T>& c, int tid, int nt, int mask) {
+__device__ __forceinline__ void phase_set_state(const Dims& D, St<T>& c, int tid, int nt, int mask) {
   for (int idx = tid; idx < D.n_bus * S; idx += nt) {
     if (!((mask >> (idx % S)) & 1)) continue;
     double sn, cs;
@@ -701,7 +900,7 @@ __device__ void phase_set_state(const Dims& D, St<T>& c, int tid, int nt, int ma
 // the Newton kernel: one workgroup = one slice of S scenarios
 
 template <typename T, bool RES, int S>
-__global__ void __launch_bounds__(1024) k_newton(KParams kp) {
+__global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int slice = blockIdx.x;
@@ -767,6 +966,8 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
 
   const bool mixed = sizeof(T) == 4;
   const int gmin = kp.gmin > S ? kp.gmin : S;
+  const int wv = tid >> 6, ln = tid & 63;   // LDS-resident tails: wavefront wv <-> scenario wv
+  TailRow<T> R;                             // this wavefront's factored tail rows
   while (true) {
     phase_mismatch<T, S>(m, D, c, tid, nt, scr);
     for (int s = 0; s < S; ++s) {
@@ -787,7 +988,11 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
     for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
     phase_fill<T, S>(m, D, c, tid, nt);
     phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, true, piv);
-    phase_tail_factor<T, S, RES>(m, D, c, tid, nt, true, piv);
+    if constexpr (RES) {
+      if (wv < S) rt_factor<T, S>(m, D, c, wv, ln, true, piv, R);
+    } else {
+      phase_tail_factor<T, S, RES>(m, D, c, tid, nt, true, piv);
+    }
     __syncthreads();
     for (int s = 0; s < S; ++s)
       if (((act >> s) & 1) && piv[s]) {
@@ -795,7 +1000,11 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
         if (tid == 0) s_st[s] = 3;
       }
     if (!act) break;
-    phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
+    if constexpr (RES) {
+      if (wv < S) rt_bsolve<T, S>(m, D, c, wv, ln, R);
+    } else {
+      phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
+    }
     __syncthreads();
     phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
     for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
@@ -805,9 +1014,16 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
         phase_dv<T, S>(m, D, c, tid, nt);
         phase_residual<T, S>(m, D, c, tid, nt);
         phase_fsolve<T, S>(m, D, c, tid, nt, gmin);
-        phase_tail_fsolve<T, S, RES>(m, D, c, tid, nt);
-        __syncthreads();
-        phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
+        if constexpr (RES) {
+          if (wv < S) {
+            rt_fsolve<T, S>(m, D, c, wv, ln, R);
+            rt_bsolve<T, S>(m, D, c, wv, ln, R);
+          }
+        } else {
+          phase_tail_fsolve<T, S, RES>(m, D, c, tid, nt);
+          __syncthreads();
+          phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
+        }
         __syncthreads();
         phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
         for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] += double(c.y[q]);
@@ -869,7 +1085,14 @@ __global__ void __launch_bounds__(1024) k_newton(KParams kp) {
     if (tid < S) piv[tid] = 0;
     phase_fill<T, S>(m, D, c, tid, nt);
     phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, false, piv);
-    phase_tail_factor<T, S, RES>(m, D, c, tid, nt, false, piv);
+    if constexpr (RES) {
+      if (wv < S) {
+        rt_factor<T, S>(m, D, c, wv, ln, false, piv, R);
+        rt_store<T, S>(m, D, c, wv, ln, R);
+      }
+    } else {
+      phase_tail_factor<T, S, RES>(m, D, c, tid, nt, false, piv);
+    }
     __syncthreads();
     if (tid < S && s_st[tid] == 0 && piv[tid]) s_st[tid] = 3;
     if (RES || S > 1) {   // scatter the slice into the per-scenario workspace
@@ -1051,6 +1274,7 @@ template <typename T>
 static hipError_t launch_newton_t(const KParams& kp, int slice, int grid, int nt, size_t lds,
                                   bool res, hipStream_t st) {
   dim3 g(grid), b(nt);
+  if (res && (nt != kResThreads || slice > kResMaxSlice)) return hipErrorInvalidValue;
   if (!res) {
     switch (slice) {
       case 1: hipLaunchKernelGGL((k_newton<T, false, 1>), g, b, lds, st, kp); break;
@@ -1065,7 +1289,6 @@ static hipError_t launch_newton_t(const KParams& kp, int slice, int grid, int nt
       case 1: hipLaunchKernelGGL((k_newton<T, true, 1>), g, b, lds, st, kp); break;
       case 2: hipLaunchKernelGGL((k_newton<T, true, 2>), g, b, lds, st, kp); break;
       case 4: hipLaunchKernelGGL((k_newton<T, true, 4>), g, b, lds, st, kp); break;
-      case 8: hipLaunchKernelGGL((k_newton<T, true, 8>), g, b, lds, st, kp); break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -1107,7 +1330,6 @@ static hipError_t set_lds_t(int max_lds) {
   set(reinterpret_cast<const void*>(&k_newton<T, true, 1>));
   set(reinterpret_cast<const void*>(&k_newton<T, true, 2>));
   set(reinterpret_cast<const void*>(&k_newton<T, true, 4>));
-  set(reinterpret_cast<const void*>(&k_newton<T, true, 8>));
   return e;
 }
 

@@ -312,6 +312,14 @@ int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
         S.tail_pos[(size_t)i * t + (S.ci[p] - S.tail_base)] = p;
       }
     }
+    S.tail_mask.assign(t ? t + 2 : 0, 0u);
+    if (t > 0 && t <= 32)
+      for (int32_t i = 0; i < t; ++i)
+        for (int32_t j = 0; j < t; ++j) {
+          if (S.tail_pos[(size_t)i * t + j] < 0 || i == j) continue;
+          if (j > i) { S.tail_mask[i] |= 1u << j; S.tail_mask[t + 1] |= 1u << j; }
+          else S.tail_mask[t] |= 1u << j;
+        }
   }
   const int32_t tb = S.tail_base;
   {

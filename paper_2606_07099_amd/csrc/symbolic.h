@@ -70,6 +70,11 @@ struct Symbolic {
   int32_t tail_t = 0, tail_base = 0, tail_h = 0;
   int32_t n_task_levels = 0, n_fs_levels = 0;
   std::vector<int32_t> tail_pos, tail_split;
+  // structure of the tail block as bit masks over tail columns (tail_t <= 32):
+  // tail_mask[k] bit j: block (k, j), j > k, of the tail is nonzero;
+  // tail_mask[t] bit j: column j has a nonzero below the diagonal;
+  // tail_mask[t + 1] bit j: column j has a nonzero above the diagonal
+  std::vector<uint32_t> tail_mask;
   // elimination steps of the tail pivots, pivot by pivot: tk_ptr[k] .. tk_ptr[k+1]
   // index tstep4 records {row i, q = L position of (i, pivot) - rp[i], first
   // target in upd_tgt, 0}
