@@ -132,6 +132,12 @@ def main():
     t_build = time.perf_counter() - t_build
     tplmp = PFTemplate.from_network(net, B, tol=spec.tol, precision="mixed", keep_factors=False)
     tpllay = PFTemplate.from_network(net, B, tol=spec.tol, precision="mixed", keep_factors=True)
+    # variants reported beside the configured 2-step refinement: adaptive
+    # refinement (at most 2 steps) and no refinement at all
+    tplad = PFTemplate.from_network(net, B, tol=spec.tol, precision="mixed", keep_factors=False,
+                                    refine_adaptive=True)
+    tplr0 = PFTemplate.from_network(net, B, tol=spec.tol, precision="mixed", keep_factors=False,
+                                    refine_steps=0)
     layer = PFLayer(tpllay)
     info64, infomp = tpl64.info(), tplmp.info()
 
@@ -139,6 +145,8 @@ def main():
         [torch.empty(B, dtype=torch.int32, device=dev) for _ in range(2)] + \
         [torch.empty(B, dtype=torch.float64, device=dev)]
     outmp = [x.clone() for x in out64]
+    outad = [x.clone() for x in out64]
+    outr0 = [x.clone() for x in out64]
     leaves = {k: d[k].clone().requires_grad_(True) for k in d}
 
     def layer_step():
@@ -159,6 +167,8 @@ def main():
     for _ in range(args.warmup):
         tpl64.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=out64)
         tplmp.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=outmp)
+        tplad.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=outad)
+        tplr0.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=outr0)
         layer_step()
     torch.cuda.synchronize()
 
@@ -166,7 +176,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        e = [ev() for _ in range(4)]
+        e = [ev() for _ in range(6)]
         e[0].record(stream)
         tpl64.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=out64)
         e[1].record(stream)
@@ -174,6 +184,10 @@ def main():
         e[2].record(stream)
         layer_step()
         e[3].record(stream)
+        tplad.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=outad)
+        e[4].record(stream)
+        tplr0.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=outr0)
+        e[5].record(stream)
         marks.append(e)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -181,6 +195,10 @@ def main():
     t64 = np.array([m[0].elapsed_time(m[1]) for m in marks]) * 1e-3
     tmp = np.array([m[1].elapsed_time(m[2]) for m in marks]) * 1e-3
     tfb = np.array([m[2].elapsed_time(m[3]) for m in marks]) * 1e-3
+    tad = np.array([m[3].elapsed_time(m[4]) for m in marks]) * 1e-3
+    tr0 = np.array([m[4].elapsed_time(m[5]) for m in marks]) * 1e-3
+    itad, stad, fnad = (x.cpu().numpy() for x in outad[2:])
+    itr0, str0, fnr0 = (x.cpu().numpy() for x in outr0[2:])
     it64, st64, fn64 = (x.cpu().numpy() for x in out64[2:])
     itmp, stmp, fnmp = (x.cpu().numpy() for x in outmp[2:])
     mp_rate = B / tmp.mean()
@@ -207,11 +225,18 @@ def main():
         "fp64_solves_per_s": B / t64.mean(),
         "mixed_solves_per_s": mp_rate,
         "layer_fwd_bwd_samples_per_s": B / tfb.mean(),
+        "mixed_adaptive_solves_per_s": B / tad.mean(),
+        "mixed_unrefined_solves_per_s": B / tr0.mean(),
         "ms": {"fp64_solve": 1e3 * t64.mean(), "mixed_solve": 1e3 * tmp.mean(),
+               "mixed_adaptive_solve": 1e3 * tad.mean(), "mixed_unrefined_solve": 1e3 * tr0.mean(),
                "layer_fwd_bwd": 1e3 * tfb.mean(), "template_build": 1e3 * t_build},
-        "iterations": {"fp64": np.bincount(it64).tolist(), "mixed": np.bincount(itmp).tolist()},
-        "converged": {"fp64": int((st64 == 0).sum()), "mixed": int((stmp == 0).sum())},
-        "max_final_mismatch": {"fp64": float(fn64.max()), "mixed": float(fnmp.max())},
+        "iterations": {"fp64": np.bincount(it64).tolist(), "mixed": np.bincount(itmp).tolist(),
+                       "mixed_adaptive": np.bincount(itad).tolist(),
+                       "mixed_unrefined": np.bincount(itr0).tolist()},
+        "converged": {"fp64": int((st64 == 0).sum()), "mixed": int((stmp == 0).sum()),
+                      "mixed_adaptive": int((stad == 0).sum()), "mixed_unrefined": int((str0 == 0).sum())},
+        "max_final_mismatch": {"fp64": float(fn64.max()), "mixed": float(fnmp.max()),
+                               "mixed_adaptive": float(fnad.max()), "mixed_unrefined": float(fnr0.max())},
         "template": {k: infomp[k] for k in ("n_j", "nnz_j1", "nnzb_lu", "nnz_lu", "fill_ratio",
                                             "n_levels_l", "n_levels_u", "lds_resident",
                                             "block_threads", "lds_bytes", "slice_width", "workspace_bytes")},

@@ -87,6 +87,14 @@ typedef struct {
   int32_t block_threads; /* threads per workgroup, 0 = automatic (64..1024); LDS-resident
                             slices always run 256 threads, so any other nonzero value
                             selects HBM-resident slices */
+  int32_t refine_adaptive; /* PF_MIXED forward solve: 0 (default) applies all refine_steps
+                            refinement solves; 1 computes the FP64 residual r of the
+                            current correction and refines only while
+                            ||r||_inf > max(min(0.1, ||F1||_inf) ||F1||_inf, 0.1 tol)
+                            (an inexact-Newton forcing term that keeps the convergence
+                            quadratic), at most refine_steps times.  The convergence test
+                            is always on the FP64 mismatch, so the final accuracy is the
+                            same; the adjoint always applies refine_steps steps */
 } pf_options;
 
 typedef struct {

@@ -25,7 +25,8 @@ EXPORTED = ("pf_default_options", "pf_last_error", "pf_ybus_from_branches", "pf_
 class PFOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("keep_factors", ctypes.c_int32), ("block_threads", ctypes.c_int32)]
+                ("keep_factors", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("refine_adaptive", ctypes.c_int32)]
 
 
 class PFStats(ctypes.Structure):

@@ -74,8 +74,8 @@ sable::StateLayout make_layout(int n_bus, int nb, int nnzb) {
   int o = 0;
   L.o_e = o; o += nbr; L.o_f = o; o += nbr; L.o_vm = o; o += nbr; L.o_va = o; o += nbr;
   L.o_ire = o; o += nbr; L.o_iim = o; o += nbr; L.o_ps = o; o += nbr; L.o_qs = o; o += nbr;
-  L.o_dvr = o; o += nbr; L.o_dvi = o; o += nbr; L.o_aux = o; o += nbr;
-  L.o_F = o; o += v2; L.o_dx = o; o += v2; L.o_rr = o; o += v2;
+  L.o_dvr = o; o += nbr; L.o_dvi = o; o += nbr; L.o_aux = o; o += nbr; L.o_rvm = o; o += nbr;
+  L.o_F = o; o += v2; L.o_dx = o; o += v2;
   L.sd = o;
   int t = 0;
   L.o_y = t; t += round_up(2 * nb, 8);
@@ -92,11 +92,12 @@ sable::StateLayout make_lds_layout(int n_bus, int nb, int nnzb, bool mixed) {
   int o = 0;
   L.o_e = o; o += n_bus; L.o_f = o; o += n_bus; L.o_vm = o; o += n_bus; L.o_va = o; o += n_bus;
   L.o_ire = o; o += n_bus; L.o_iim = o; o += n_bus; L.o_ps = o; o += n_bus; L.o_qs = o; o += n_bus;
+  L.o_rvm = o; o += n_bus;
   L.o_F = o; o += 2 * nb; L.o_dx = o; o += 2 * nb;
   if (mixed) {
-    L.o_dvr = o; o += n_bus; L.o_dvi = o; o += n_bus; L.o_rr = o; o += 2 * nb;
+    L.o_dvr = o; o += n_bus; L.o_dvi = o; o += n_bus;
   } else {
-    L.o_dvr = L.o_dvi = L.o_rr = 0;
+    L.o_dvr = L.o_dvi = 0;
   }
   L.o_aux = 0;
   L.sd = round_up(o, 2);
@@ -162,6 +163,7 @@ sable::KParams base_params(const pf_template* t) {
   kp.wsl_t = t->wsl_t ? t->wsl_t : t->ws_t;
   kp.max_iter = t->opt.max_iter;
   kp.refine = t->fp32 ? t->opt.refine_steps : 0;
+  kp.adaptive = t->opt.refine_adaptive;
   kp.keep = t->opt.keep_factors;
   kp.gmin = t->gmin;
   kp.wstride = t->wstride;
@@ -180,6 +182,7 @@ void pf_default_options(pf_options* opt) {
   opt->max_iter = 20;
   opt->precision = PF_FP64;
   opt->refine_steps = 2;
+  opt->refine_adaptive = 0;
   opt->keep_factors = 1;
   opt->block_threads = 0;
 }
@@ -236,6 +239,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   if (batch <= 0) return fail(PF_EINVAL, "pf_template_build: batch must be positive");
   if (!(opt.tol > 0.0) || opt.max_iter < 0 || (opt.precision != PF_FP64 && opt.precision != PF_MIXED) ||
       opt.refine_steps < 0 || opt.refine_steps > 16 || opt.block_threads < 0 ||
+      (opt.refine_adaptive != 0 && opt.refine_adaptive != 1) ||
       opt.block_threads > 1024 || (opt.block_threads % 64) != 0)
     return fail(PF_EINVAL, "pf_template_build: invalid options");
 
@@ -327,14 +331,16 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     nt = sable::kResThreads;
   } else {
     // HBM-resident: S scenarios interleaved per slice, S as large as keeps
-    // at least one slice per compute unit, one wavefront per scenario
+    // at least one slice per compute unit
     t->lds_res = false;
     const int n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     int sl = 1;
     while (sl < sable::kMaxSlice && batch / (2 * sl) >= n_cu) sl *= 2;
     t->slice = sl;
     t->lds_bytes = sable::kScratchBytes;
-    if (nt == 0) nt = std::min(1024, std::max(256, 64 * sl));
+    // a full workgroup of 16 wavefronts: measured fastest for every slice
+    // width (more lanes per level of the elimination schedule)
+    if (nt == 0) nt = 1024;
   }
   t->nt = nt;
 

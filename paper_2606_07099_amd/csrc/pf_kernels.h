@@ -55,12 +55,12 @@ struct Dims {
 };
 
 // Offsets of the per-scenario arrays, in elements.  FP64 arrays:
-// e f vm va ire iim ps qs dvr dvi aux [n_bus], F dx rr [2 nb].  Factor-
+// e f vm va ire iim ps qs dvr dvi aux rvm (= 1/|V|) [n_bus], F dx [2 nb].  Factor-
 // precision arrays (T): y [2 nb], lu [4 nnzb], dinv [4 nb].  In an
 // LDS-resident slice of S scenarios every array is interleaved by scenario
 // (element k of scenario s at k*S + s) and starts at offset*S.
 struct StateLayout {
-  int o_e, o_f, o_vm, o_va, o_ire, o_iim, o_ps, o_qs, o_dvr, o_dvi, o_aux, o_F, o_dx, o_rr;
+  int o_e, o_f, o_vm, o_va, o_ire, o_iim, o_ps, o_qs, o_dvr, o_dvi, o_aux, o_rvm, o_F, o_dx;
   int sd;  // doubles per scenario
   int o_y, o_lu, o_dinv;
   int st;  // T elements per scenario
@@ -77,7 +77,7 @@ struct KParams {
   int* ws_i;
   double* wsl_d;             // HBM-resident slices: S scenarios interleaved per slice
   void* wsl_t;
-  int mode, max_iter, refine, keep, count, gmin, wstride;
+  int mode, max_iter, refine, adaptive, keep, count, gmin, wstride;
   double tol;
   const double *pd, *qd, *pg, *vset, *vm_in, *va_in, *rhs, *g_vm, *g_va;
   double *vm_out, *va_out, *fnorm_out, *out, *g_pd, *g_qd, *g_pg, *g_vset;

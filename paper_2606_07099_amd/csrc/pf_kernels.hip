@@ -99,7 +99,7 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
 // per-slice state; element k of scenario s sits at k*S + s
 template <typename T>
 struct St {
-  double *e, *f, *vm, *va, *ire, *iim, *ps, *qs, *dvr, *dvi, *aux, *F, *dx, *rr;
+  double *e, *f, *vm, *va, *ire, *iim, *ps, *qs, *dvr, *dvi, *aux, *rvm, *F, *dx;
   T *y, *lu, *dinv;
 };
 
@@ -108,8 +108,8 @@ __device__ __forceinline__ St<T> bind_state(double* d, T* t, const StateLayout& 
   St<T> c;
   c.e = d + L.o_e * S; c.f = d + L.o_f * S; c.vm = d + L.o_vm * S; c.va = d + L.o_va * S;
   c.ire = d + L.o_ire * S; c.iim = d + L.o_iim * S; c.ps = d + L.o_ps * S; c.qs = d + L.o_qs * S;
-  c.dvr = d + L.o_dvr * S; c.dvi = d + L.o_dvi * S; c.aux = d + L.o_aux * S;
-  c.F = d + L.o_F * S; c.dx = d + L.o_dx * S; c.rr = d + L.o_rr * S;
+  c.dvr = d + L.o_dvr * S; c.dvi = d + L.o_dvi * S; c.aux = d + L.o_aux * S; c.rvm = d + L.o_rvm * S;
+  c.F = d + L.o_F * S; c.dx = d + L.o_dx * S;
   c.y = t + L.o_y * S; c.lu = t + L.o_lu * S; c.dinv = t + L.o_dinv * S;
   return c;
 }
@@ -121,21 +121,22 @@ __device__ __forceinline__ St<T> bind_state(double* d, T* t, const StateLayout& 
 // terms; the values equal the closed forms of Algorithm 1.
 struct J4 { double v[4]; };
 
-__device__ __forceinline__ J4 jac_diag(double G, double B, double ei, double fi, double vmi,
+// (rv = 1 / |V| of the bus whose magnitude is the column unknown)
+__device__ __forceinline__ J4 jac_diag(double G, double B, double ei, double fi, double vmi, double rvi,
                                        double iri, double iii) {
   const double P = ei * iri + fi * iii;
   const double Q = fi * iri - ei * iii;
   const double v2 = vmi * vmi;
-  return {{Q + B * v2, -P / vmi - G * vmi, -P + G * v2, -Q / vmi + B * vmi}};
+  return {{Q + B * v2, -P * rvi - G * vmi, -P + G * v2, -Q * rvi + B * vmi}};
 }
 
 __device__ __forceinline__ J4 jac_off(double G, double B, double ei, double fi, double em, double fm,
-                                      double vmm) {
+                                      double rvm) {
   const double cc = ei * em + fi * fm;
   const double ss = fi * em - ei * fm;
   const double gs_bc = G * ss - B * cc;
   const double gc_bs = G * cc + B * ss;
-  return {{-gs_bc, -gc_bs / vmm, gc_bs, -gs_bc / vmm}};
+  return {{-gs_bc, -gc_bs * rvm, gc_bs, -gs_bc * rvm}};
 }
 
 // The 2x2 block of the padded block system at LU position p for scenario s.
@@ -149,8 +150,8 @@ __device__ __forceinline__ Blk<T> fill_block(const Sym& m, const St<T>& c, int p
   const double G = r.x < 0 ? 0.0 : m.y_g[r.x];
   const double Bv = r.x < 0 ? 0.0 : m.y_b[r.x];
   const int is = sI<S>(r.y, s), ms = sI<S>(r.z, s);
-  J4 x = dg ? jac_diag(G, Bv, c.e[is], c.f[is], c.vm[is], c.ire[is], c.iim[is])
-            : jac_off(G, Bv, c.e[is], c.f[is], c.e[ms], c.f[ms], c.vm[ms]);
+  J4 x = dg ? jac_diag(G, Bv, c.e[is], c.f[is], c.vm[is], c.rvm[is], c.ire[is], c.iim[is])
+            : jac_off(G, Bv, c.e[is], c.f[is], c.e[ms], c.f[ms], c.rvm[ms]);
   if (r.w & 2) { x.v[2] = 0.0; x.v[3] = 0.0; }
   if (r.w & 4) { x.v[1] = 0.0; x.v[3] = 0.0; }
   if ((r.w & 3) == 3) x.v[3] = 1.0;
@@ -287,8 +288,10 @@ __device__ __forceinline__ void phase_factor(const Sym& m, const Dims& D, St<T>&
       T* W = c.lu + sB<S>(rs, 0);
       T y0 = T(0), y1 = T(0);
       if (fwd) { y0 = c.y[sP<S>(a, s)]; y1 = c.y[sP<S>(a, s) + 1]; }
+      // with one lane per scenario (E == 1) every target of the task is
+      // written and re-read by the same lane, so HBM state needs no fence
       for (int i = tk.y; i < tk.z; ++i) {
-        if (i > tk.y) wave_order<RES>();   // the previous step's targets may feed this one
+        if (i > tk.y && E > 1) wave_order<RES>();   // the previous step's targets may feed this one
         const int4 st = m.step4[i];   // q, k, start of U(k,>k), |U(k,>k)|
         const int ts = m.step_ts[i];
         const int k = st.y;
@@ -298,7 +301,26 @@ __device__ __forceinline__ void phase_factor(const Sym& m, const Dims& D, St<T>&
           y0 -= L.a * yk0 + L.b * yk1;
           y1 -= L.c * yk0 + L.d * yk1;
         }
-        for (int t = e; t < st.w; t += E) {
+        // the targets of one step are distinct: NB at a time, loads first
+        constexpr int NB = 2;
+        int t = e;
+        for (; t + (NB - 1) * E < st.w; t += NB * E) {
+          Blk<T> U[NB], x[NB];
+          T* w[NB];
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            U[u] = ld_blk(c.lu + sB<S>(st.z + t + u * E, s));
+            w[u] = W + sB<S>(m.upd_tgt[ts + t + u * E], s);
+            x[u] = ld_blk(w[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            const Blk<T> LU = mul(L, U[u]);
+            x[u].a -= LU.a; x[u].b -= LU.b; x[u].c -= LU.c; x[u].d -= LU.d;
+            st_blk(w[u], x[u]);
+          }
+        }
+        for (; t < st.w; t += E) {
           const Blk<T> U = ld_blk(c.lu + sB<S>(st.z + t, s));
           T* w = W + sB<S>(m.upd_tgt[ts + t], s);
           Blk<T> x = ld_blk(w);
@@ -310,7 +332,7 @@ __device__ __forceinline__ void phase_factor(const Sym& m, const Dims& D, St<T>&
       }
       if (e == 0) {
         if (tk.w) {
-          if (tk.z - tk.y > 1) wave_order<RES>();
+          if (tk.z - tk.y > 1 && E > 1) wave_order<RES>();
           const Blk<T> Dk = ld_blk(W + sB<S>(m.diag[a] - rs, s));
           const T det = Dk.a * Dk.d - Dk.b * Dk.c;
           const T inv = T(1) / det;
@@ -796,7 +818,7 @@ __device__ __forceinline__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, 
     double dvr = 0.0, dvi = 0.0;
     if (a >= 0) {
       const double dth = c.dx[sP<S>(a, s)];
-      const double rho = m.bus_type[i] == 0 ? c.dx[sP<S>(a, s) + 1] / c.vm[idx] : 0.0;
+      const double rho = m.bus_type[i] == 0 ? c.dx[sP<S>(a, s) + 1] * c.rvm[idx] : 0.0;
       dvr = c.e[idx] * rho - c.f[idx] * dth;
       dvi = c.f[idx] * rho + c.e[idx] * dth;
     }
@@ -807,9 +829,12 @@ __device__ __forceinline__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, 
 }
 
 // r = -F1 - J1 dx in FP64 without forming J1: J1 dx = -(dS restricted to the
-// F1 rows), dS = dV conj(I) + V conj(Y dV).  Result cast into y.
+// F1 rows), dS = dV conj(I) + V conj(Y dV).  Result cast into y; with norm,
+// ||r||_inf per scenario lands in the scratch maxima.
 template <typename T, int S>
-__device__ __forceinline__ void phase_residual(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+__device__ __forceinline__ void phase_residual(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
+                                               bool norm, unsigned char* scr) {
+  double mx = 0.0;
   for (int idx = tid; idx < D.n_bus * S; idx += nt) {
     const int i = idx / S, s = idx % S;
     const int a = m.bus_blk[i];
@@ -828,12 +853,12 @@ __device__ __forceinline__ void phase_residual(const Sym& m, const Dims& D, St<T
     const int o = sP<S>(a, s);
     const double r0 = -c.F[o] + dSr;
     const double r1 = m.bus_type[i] == 0 ? -c.F[o + 1] + dSi : 0.0;
-    c.rr[o] = r0;
-    c.rr[o + 1] = r1;
     c.y[o] = T(r0);
     c.y[o + 1] = T(r1);
+    mx = fmax(mx, fmax(fabs(r0), fabs(r1)));
   }
   __syncthreads();
+  if (norm) block_max<S>(mx, 0, scr, tid, nt);
 }
 
 // adjoint residual r = g - J1^T lam in FP64 without forming J1 (transposed
@@ -875,8 +900,6 @@ __device__ __forceinline__ void phase_adj_residual(const Sym& m, const Dims& D, 
     if (a >= 0 && g) {
       const double r0 = g[2 * a] - vci;
       const double r1 = m.bus_type[mb] == 0 ? g[2 * a + 1] + vcr / c.vm[mb] : 0.0;
-      c.rr[2 * a] = r0;
-      c.rr[2 * a + 1] = r1;
       if (to_y) { c.y[2 * a] = T(r0); c.y[2 * a + 1] = T(r1); }
     }
   }
@@ -890,8 +913,10 @@ __device__ __forceinline__ void phase_set_state(const Dims& D, St<T>& c, int tid
     if (!((mask >> (idx % S)) & 1)) continue;
     double sn, cs;
     sincos(c.va[idx], &sn, &cs);
-    c.e[idx] = c.vm[idx] * cs;
-    c.f[idx] = c.vm[idx] * sn;
+    const double v = c.vm[idx];
+    c.e[idx] = v * cs;
+    c.f[idx] = v * sn;
+    c.rvm[idx] = 1.0 / v;
   }
   __syncthreads();
 }
@@ -1010,9 +1035,20 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
     for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
     __syncthreads();
     if (mixed) {
+      int ref = act;   // scenarios still refining their correction
       for (int r = 0; r < kp.refine; ++r) {
         phase_dv<T, S>(m, D, c, tid, nt);
-        phase_residual<T, S>(m, D, c, tid, nt);
+        phase_residual<T, S>(m, D, c, tid, nt, kp.adaptive, scr);
+        if (kp.adaptive) {
+          // inexact-Newton forcing term: refine while the FP64 residual of the
+          // correction exceeds max(min(0.1, |F|) |F|, 0.1 tol)
+          for (int s = 0; s < S; ++s) {
+            const double f = s_fn[s];
+            const double thr = fmax(fmin(0.1, f) * f, 0.1 * kp.tol);
+            if (!(fnr[s] > thr)) ref &= ~(1 << s);
+          }
+          if (!ref) break;
+        }
         phase_fsolve<T, S>(m, D, c, tid, nt, gmin);
         if constexpr (RES) {
           if (wv < S) {
@@ -1026,7 +1062,8 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
         }
         __syncthreads();
         phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
-        for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] += double(c.y[q]);
+        for (int q = tid; q < 2 * nb * S; q += nt)
+          if ((ref >> ((q >> 1) % S)) & 1) c.dx[q] += double(c.y[q]);
         __syncthreads();
       }
     }
@@ -1253,8 +1290,8 @@ __global__ void __launch_bounds__(256) k_jacobian_dense(KParams kp) {
     for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
       const int j = m.y_ci[q];
       if (m.bus_type[j] == 2) continue;
-      const J4 x = (i == j) ? jac_diag(m.y_g[q], m.y_b[q], e[i], f[i], vm[i], ire[i], iim[i])
-                            : jac_off(m.y_g[q], m.y_b[q], e[i], f[i], e[j], f[j], vm[j]);
+      const J4 x = (i == j) ? jac_diag(m.y_g[q], m.y_b[q], e[i], f[i], vm[i], 1.0 / vm[i], ire[i], iim[i])
+                            : jac_off(m.y_g[q], m.y_b[q], e[i], f[i], e[j], f[j], 1.0 / vm[j]);
       const int cT = D.npq + m.ord_p[j];
       const int cV = m.bus_type[j] == 0 ? m.ord_q[j] : -1;
       o[(size_t)rP * nj + cT] = x.v[0];

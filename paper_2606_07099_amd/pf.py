@@ -73,7 +73,8 @@ class PFTemplate:
     workspace of ``pf_template_build``."""
 
     def __init__(self, n_bus, bus_type, indptr, indices, g, b, batch, *, tol=1e-8, max_iter=20,
-                 precision="fp64", refine_steps=2, keep_factors=True, block_threads=0):
+                 precision="fp64", refine_steps=2, keep_factors=True, block_threads=0,
+                 refine_adaptive=False):
         L = lib()
         opt = PFOptions()
         L.pf_default_options(ctypes.byref(opt))
@@ -83,6 +84,7 @@ class PFTemplate:
         opt.refine_steps = int(refine_steps)
         opt.keep_factors = 1 if keep_factors else 0
         opt.block_threads = int(block_threads)
+        opt.refine_adaptive = 1 if refine_adaptive else 0
         self.n_bus = int(n_bus)
         self.batch = int(batch)
         self.precision = precision

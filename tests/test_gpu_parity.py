@@ -132,6 +132,26 @@ def test_newton_mixed_precision_matches_oracle(name, n_check, device):
     assert np.all(res[4].cpu().numpy() < tol)
 
 
+@pytest.mark.parametrize("name,refine,adaptive,n_check", [("c1", 2, True, 48), ("c1", 0, False, 48),
+                                                          ("c3", 2, True, 12), ("c2", 2, True, 6),
+                                                          ("c2", 0, False, 6)])
+def test_mixed_adaptive_and_unrefined_match_oracle(name, refine, adaptive, n_check, device):
+    """Adaptive refinement (inexact-Newton forcing term) and no refinement at
+    all (FP32 steps corrected only by the FP64 outer Newton loop): the
+    convergence test stays on the FP64 mismatch, so the solutions match the
+    FP64 oracle to the same bar, at most one extra Newton update."""
+    import torch
+    spec, net, sc, tpl, d, tol = make_gpu_case(name, device, precision="mixed", refine_steps=refine,
+                                               refine_adaptive=adaptive)
+    res = tpl.solve(d["pd"], d["qd"], d["pg"], d["vset"])
+    torch.cuda.synchronize()
+    which = np.unique(np.linspace(0, sc.batch - 1, n_check).astype(int))
+    oracle = newton_batch(ybus_of(net), net.bus_type, sc, tol=tol, which=which)
+    _check_solution(net, sc, which, res, oracle, tol, iters_slack=1)
+    assert np.all(res[3].cpu().numpy() == 0)
+    assert np.all(res[4].cpu().numpy() < tol)
+
+
 def test_large_grid_solution_satisfies_the_equations(device):
     """9241-bus grid, batch 256: every scenario converges and the oracle's own
     mismatch at the returned voltages is below the tolerance (a property that

@@ -41,8 +41,8 @@ def test_default_options(L):
     from paper_2606_07099_amd._lib import PFOptions
     o = PFOptions()
     L.pf_default_options(ctypes.byref(o))
-    assert (o.tol, o.max_iter, o.precision, o.refine_steps, o.keep_factors, o.block_threads) == \
-        (1e-8, 20, 0, 2, 1, 0)
+    assert (o.tol, o.max_iter, o.precision, o.refine_steps, o.keep_factors, o.block_threads,
+            o.refine_adaptive) == (1e-8, 20, 0, 2, 1, 0, 0)
 
 
 @pytest.mark.parametrize("name", ["c0", "c1", "c3"])
