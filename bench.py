@@ -33,9 +33,11 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE passes (each scaled by
 # the same counter on a 512 MiB device-to-device copy), keyed by the SHA-256
 # of the kernel sources they were taken on; a changed kernel reports null.
-# Source: profiles/k_newton_118bus_b1024_hbm_counters.md
+# Sources: profiles/k_newton_118bus_b1024_hbm_counters.md,
+# profiles/k_newton_1354bus_b4096_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "62931a784219604147770ceee49a50ea18b760bb6f1613ad2181c616bc718fb9": {"c1": 6654858},
+    "7d0c427523c47a4290b4b5a306514474e14632319026362bcc8fe7e9184ba928": {"c1": 6670899,
+                                                                         "c2": 46669982461},
 }
 
 
