@@ -39,6 +39,12 @@ __device__ __forceinline__ Blk<T> mul(const Blk<T>& x, const Blk<T>& y) {
   return {x.a * y.a + x.b * y.c, x.a * y.b + x.b * y.d, x.c * y.a + x.d * y.c, x.c * y.b + x.d * y.d};
 }
 
+// reciprocal of a pivot determinant: the hardware reciprocal (1 ulp) for
+// FP32 factors, which the FP64 residual of the Newton loop corrects; an
+// exact division for FP64 factors
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // interleaved indexing inside a slice of S scenarios
 template <int S> __device__ __forceinline__ int sI(int i, int s) { return i * S + s; }
 template <int S> __device__ __forceinline__ int sP(int a, int s) { return (a * S + s) * 2; }
@@ -141,17 +147,38 @@ __device__ __forceinline__ J4 jac_off(double G, double B, double ei, double fi, 
 
 // The 2x2 block of the padded block system at LU position p for scenario s.
 // PV buses keep a dummy |V| unknown and a dummy dQ row: identity on the
-// diagonal, zero coupling; fill-in positions start at zero.
+// diagonal, zero coupling; fill-in positions start at zero.  Split into the
+// gathers (fill record, then the Y entry and the two buses' state) and the
+// arithmetic, so that several blocks' gathers are in flight together.
+struct FillIn {
+  int4 r;           // Y entry, row bus, column bus, flags
+  double g, b;      // Y entry
+  double x[6];      // diagonal: e f |V| 1/|V| I_re I_im of the bus; else e f of the row bus, e f 1/|V| of the column bus
+};
+
 template <typename T, int S>
-__device__ __forceinline__ Blk<T> fill_block(const Sym& m, const St<T>& c, int p, int s) {
-  const int4 r = m.fill4[p];   // Y entry, row bus, column bus, flags
+__device__ __forceinline__ void fill_gather(const Sym& m, const St<T>& c, int s, FillIn& q) {
+  const int4 r = q.r;
+  const bool dg = r.w & 1;
+  q.g = r.x < 0 ? 0.0 : m.y_g[r.x];
+  q.b = r.x < 0 ? 0.0 : m.y_b[r.x];
+  const int is = sI<S>(r.y, s), ms = sI<S>(r.z, s);
+  q.x[0] = c.e[is];
+  q.x[1] = c.f[is];
+  if (dg) {
+    q.x[2] = c.vm[is]; q.x[3] = c.rvm[is]; q.x[4] = c.ire[is]; q.x[5] = c.iim[is];
+  } else {
+    q.x[2] = c.e[ms]; q.x[3] = c.f[ms]; q.x[4] = c.rvm[ms]; q.x[5] = 0.0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ Blk<T> fill_value(const FillIn& q) {
+  const int4 r = q.r;
   const bool dg = r.w & 1;
   if (r.x < 0 && !dg) return {T(0), T(0), T(0), T(0)};
-  const double G = r.x < 0 ? 0.0 : m.y_g[r.x];
-  const double Bv = r.x < 0 ? 0.0 : m.y_b[r.x];
-  const int is = sI<S>(r.y, s), ms = sI<S>(r.z, s);
-  J4 x = dg ? jac_diag(G, Bv, c.e[is], c.f[is], c.vm[is], c.rvm[is], c.ire[is], c.iim[is])
-            : jac_off(G, Bv, c.e[is], c.f[is], c.e[ms], c.f[ms], c.rvm[ms]);
+  J4 x = dg ? jac_diag(q.g, q.b, q.x[0], q.x[1], q.x[2], q.x[3], q.x[4], q.x[5])
+            : jac_off(q.g, q.b, q.x[0], q.x[1], q.x[2], q.x[3], q.x[4]);
   if (r.w & 2) { x.v[2] = 0.0; x.v[3] = 0.0; }
   if (r.w & 4) { x.v[1] = 0.0; x.v[3] = 0.0; }
   if ((r.w & 3) == 3) x.v[3] = 1.0;
@@ -254,11 +281,24 @@ __device__ __forceinline__ void wave_order() {
 
 // Jacobian values of every block of the pattern (fill-in blocks zeroed) for
 // the S scenarios: independent work, one pass before the factorisation.
-template <typename T, int S>
+template <typename T, int S, int NB>
 __device__ __forceinline__ void phase_fill(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
-  for (int idx = tid; idx < D.nnzb * S; idx += nt) {
-    const int p = idx / S, s = idx % S;
-    st_blk(c.lu + sB<S>(p, s), fill_block<T, S>(m, c, p, s));
+  // NB blocks per thread have their gathers in flight together
+  const int N = D.nnzb * S;
+  for (int base = tid; base < N; base += NB * nt) {
+    FillIn q[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int idx = base + u * nt;
+      q[u].r = idx < N ? m.fill4[idx / S] : make_int4(-1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) fill_gather<T, S>(m, c, (base + u * nt) % S, q[u]);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int idx = base + u * nt;
+      if (idx < N) st_blk(c.lu + sB<S>(idx / S, idx % S), fill_value<T>(q[u]));
+    }
   }
   __syncthreads();
 }
@@ -335,7 +375,7 @@ __device__ __forceinline__ void phase_factor(const Sym& m, const Dims& D, St<T>&
           if (tk.z - tk.y > 1 && E > 1) wave_order<RES>();
           const Blk<T> Dk = ld_blk(W + sB<S>(m.diag[a] - rs, s));
           const T det = Dk.a * Dk.d - Dk.b * Dk.c;
-          const T inv = T(1) / det;
+          const T inv = recip(det);
           const Blk<T> Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
           // pivots of the block: a, then the Schur complement d - c b / a
           // (|det / a| > eps (|c| + |d|) written without the division)
@@ -499,7 +539,7 @@ __device__ __forceinline__ void phase_tail_factor(const Sym& m, const Dims& D, S
       if (l == 0) {
         const Blk<T> Dk = ld_blk(c.lu + sB<S>(dk, s));
         const T det = Dk.a * Dk.d - Dk.b * Dk.c;
-        const T inv = T(1) / det;
+        const T inv = recip(det);
         Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
         // pivots of the block: a, then the Schur complement d - c b / a
         const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
@@ -692,7 +732,7 @@ __device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c,
     const Blk<T> Ak = R.get(k);
     const Blk<T> Dk = bcast_blk(Ak, k);
     const T det = Dk.a * Dk.d - Dk.b * Dk.c;
-    const T inv = T(1) / det;
+    const T inv = recip(det);
     const Blk<T> Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
     // pivots of the block: a, then the Schur complement d - c b / a
     const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
@@ -1011,7 +1051,7 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
     if (kp.mode == MODE_EVAL_MISMATCH || kp.mode == MODE_EVAL_FACTOR) break;
     if (!act) break;
     for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
-    phase_fill<T, S>(m, D, c, tid, nt);
+    phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
     phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, true, piv);
     if constexpr (RES) {
       if (wv < S) rt_factor<T, S>(m, D, c, wv, ln, true, piv, R);
@@ -1120,7 +1160,7 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
   const bool keep = (kp.mode == MODE_SOLVE && kp.keep) || kp.mode == MODE_EVAL_FACTOR;
   if (keep) {
     if (tid < S) piv[tid] = 0;
-    phase_fill<T, S>(m, D, c, tid, nt);
+    phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
     phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, false, piv);
     if constexpr (RES) {
       if (wv < S) {
