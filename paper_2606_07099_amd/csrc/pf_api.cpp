@@ -66,6 +66,10 @@ struct DeviceGuard {
   ~DeviceGuard() { if (prev >= 0) (void)hipSetDevice(prev); }
 };
 
+// largest level-metadata chunk an HBM-resident workgroup stages in LDS
+// (int32 words; 48 KB)
+constexpr int32_t kChunkInts = 12288;
+
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 sable::StateLayout make_layout(int n_bus, int nb, int nnzb) {
@@ -295,6 +299,13 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   so.blk_bus = (int)pk.add(S.blk_bus); so.lu_src = (int)pk.add(S.lu_src);
   so.mirror = (int)pk.add(S.mirror); so.y_tr = (int)pk.add(S.y_tr);
   so.ord_p = (int)pk.add(ord_p); so.ord_q = (int)pk.add(ord_q);
+  // level metadata in chunks that HBM-resident workgroups stage in LDS
+  sable::LevelChunks chunks;
+  rc = sable::build_level_chunks(S, kChunkInts, chunks, err);
+  if (rc != 0) { delete t; return fail(PF_EINVAL, err); }
+  so.f_ptr = (int)pk.add(chunks.f_ptr); so.f_blob = (int)pk.add(chunks.f_blob);
+  so.fs_ptr = (int)pk.add(chunks.fs_ptr); so.fs_blob = (int)pk.add(chunks.fs_blob);
+  so.bs_ptr = (int)pk.add(chunks.bs_ptr); so.bs_blob = (int)pk.add(chunks.bs_blob);
   so.total_bytes = (int)pk.align();
   sable::Dims& dm = t->dims;
   dm.n_bus = S.n_bus; dm.nb = S.nb; dm.nnzb = S.nnzb(); dm.nj = S.nb + S.n_pq; dm.npq = S.n_pq;
@@ -302,6 +313,10 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   dm.nlev_f = S.n_task_levels; dm.nlev_fs = S.n_fs_levels;
   dm.nlev_bs = (int)S.lev_um_ptr.size() - 1;
   dm.tail_t = S.tail_t; dm.tail_base = S.tail_base;
+  dm.nch_f = (int)chunks.f_ptr.size() - 1;
+  dm.nch_fs = (int)chunks.fs_ptr.size() - 1;
+  dm.nch_bs = (int)chunks.bs_ptr.size() - 1;
+  dm.chunk_ints = chunks.max_ints;
 
   // ---- launch shape: LDS-resident slices of S <= 4 scenarios (256 threads,
   // one wavefront per scenario's register-resident tail) when they fit,
@@ -337,7 +352,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     int sl = 1;
     while (sl < sable::kMaxSlice && batch / (2 * sl) >= n_cu) sl *= 2;
     t->slice = sl;
-    t->lds_bytes = sable::kScratchBytes;
+    t->lds_bytes = sable::kScratchBytes + 4 * (size_t)chunks.max_ints;
     // a full workgroup of 16 wavefronts: measured fastest for every slice
     // width (more lanes per level of the elimination schedule)
     if (nt == 0) nt = 1024;

@@ -44,6 +44,7 @@ struct SymOffsets {
   int newton_bytes;
   int lev_u_ptr, lev_u_rows;
   int blk_bus, lu_src, mirror, y_tr, ord_p, ord_q;
+  int f_ptr, f_blob, fs_ptr, fs_blob, bs_ptr, bs_blob;   // level chunks staged in LDS (HBM slices)
   int total_bytes;
 };
 
@@ -52,6 +53,8 @@ struct Dims {
   int nlev_l, nlev_u;             // full level schedules (adjoint)
   int nlev_f, nlev_fs, nlev_bs;   // factor-task, forward and backward levels outside the tail
   int tail_t, tail_base;          // dense tail rows [tail_base, tail_base + tail_t)
+  int nch_f, nch_fs, nch_bs;      // metadata chunks of the factor, forward and backward levels
+  int chunk_ints;                 // largest chunk (int32 words), staged after the LDS scratch
 };
 
 // Offsets of the per-scenario arrays, in elements.  FP64 arrays:

@@ -62,6 +62,7 @@ struct Sym {
   const int4* tstep4;
   const unsigned* tail_mask;
   const int *blk_bus, *lu_src, *mirror, *y_tr, *ord_p, *ord_q;
+  const int *f_ptr, *f_blob, *fs_ptr, *fs_blob, *bs_ptr, *bs_blob;
 };
 
 __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned char* g,
@@ -99,6 +100,12 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
   m.y_tr = reinterpret_cast<const int*>(g + o.y_tr);
   m.ord_p = reinterpret_cast<const int*>(g + o.ord_p);
   m.ord_q = reinterpret_cast<const int*>(g + o.ord_q);
+  m.f_ptr = reinterpret_cast<const int*>(g + o.f_ptr);
+  m.f_blob = reinterpret_cast<const int*>(g + o.f_blob);
+  m.fs_ptr = reinterpret_cast<const int*>(g + o.fs_ptr);
+  m.fs_blob = reinterpret_cast<const int*>(g + o.fs_blob);
+  m.bs_ptr = reinterpret_cast<const int*>(g + o.bs_ptr);
+  m.bs_blob = reinterpret_cast<const int*>(g + o.bs_blob);
   return m;
 }
 
@@ -445,6 +452,145 @@ __device__ __forceinline__ void phase_bsolve(const Sym& m, const Dims& D, St<T>&
         const T t0 = c.y[sP<S>(a, s)] - s0, t1 = c.y[sP<S>(a, s) + 1] - s1;
         c.y[sP<S>(a, s)] = Di.a * t0 + Di.b * t1;
         c.y[sP<S>(a, s) + 1] = Di.c * t0 + Di.d * t1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// HBM-resident slices: the same level schedules with each level's metadata
+// (tasks, steps, targets / rows, columns) first copied into LDS by the whole
+// workgroup, so that only the value loads of a step reach HBM
+
+// copies metadata chunk c of a schedule into LDS; returns its base (int32)
+__device__ __forceinline__ const int* stage_chunk(const int* ptr, const int* blob, int c, unsigned char* lds,
+                                                  int tid, int nt) {
+  const int b0 = ptr[c], b1 = ptr[c + 1];
+  int4* dst = reinterpret_cast<int4*>(lds);
+  const int4* src = reinterpret_cast<const int4*>(blob + b0);
+  for (int q = tid; q < ((b1 - b0) >> 2); q += nt) dst[q] = src[q];
+  __syncthreads();
+  return reinterpret_cast<const int*>(lds);
+}
+
+// the right-looking task schedule of phase_factor, metadata from LDS chunks
+template <typename T, int S>
+__device__ __forceinline__ void phase_factor_st(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin,
+                                                bool fwd, int* piv, unsigned char* lds) {
+  for (int ch = 0; ch < D.nch_f; ++ch) {
+    const int* h = stage_chunk(m.f_ptr, m.f_blob, ch, lds, tid, nt);
+    const int ntask = h[0], nstep = h[1];
+    const int4* tk4 = reinterpret_cast<const int4*>(h + 4);
+    const int4* st4 = tk4 + ntask + 1;
+    const int* tg = reinterpret_cast<const int*>(st4 + nstep + 1);
+    const Grp g = groups(ntask, tid, nt, gmin);
+    const int s = g.lane % S, e = g.lane / S, E = g.G / S;
+    for (int ti = g.gid; ti < ntask; ti += g.ng) {
+      const int4 tk = tk4[ti];   // row, rp[row], pivot-block offset or -1, first step
+      const int a = tk.x, se = tk4[ti + 1].w;
+      T* W = c.lu + sB<S>(tk.y, 0);
+      T y0 = T(0), y1 = T(0);
+      if (fwd) { y0 = c.y[sP<S>(a, s)]; y1 = c.y[sP<S>(a, s) + 1]; }
+      for (int i = tk.w; i < se; ++i) {
+        if (i > tk.w && E > 1) wave_order<false>();   // the previous step's targets may feed this one
+        const int4 st = st4[i];   // q, k, first U position, first target
+        const int n = st4[i + 1].w - st.w;
+        const int k = st.y;
+        const Blk<T> L = mul(ld_blk(W + sB<S>(st.x, s)), ld_blk(c.dinv + sB<S>(k, s)));
+        if (fwd) {
+          const T yk0 = c.y[sP<S>(k, s)], yk1 = c.y[sP<S>(k, s) + 1];
+          y0 -= L.a * yk0 + L.b * yk1;
+          y1 -= L.c * yk0 + L.d * yk1;
+        }
+        constexpr int NB = 2;   // the targets of one step are distinct: loads first
+        int t = e;
+        for (; t + (NB - 1) * E < n; t += NB * E) {
+          Blk<T> U[NB], x[NB];
+          T* w[NB];
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            U[u] = ld_blk(c.lu + sB<S>(st.z + t + u * E, s));
+            w[u] = W + sB<S>(tg[st.w + t + u * E], s);
+            x[u] = ld_blk(w[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            const Blk<T> LU = mul(L, U[u]);
+            x[u].a -= LU.a; x[u].b -= LU.b; x[u].c -= LU.c; x[u].d -= LU.d;
+            st_blk(w[u], x[u]);
+          }
+        }
+        for (; t < n; t += E) {
+          const Blk<T> U = ld_blk(c.lu + sB<S>(st.z + t, s));
+          T* w = W + sB<S>(tg[st.w + t], s);
+          Blk<T> x = ld_blk(w);
+          const Blk<T> LU = mul(L, U);
+          x.a -= LU.a; x.b -= LU.b; x.c -= LU.c; x.d -= LU.d;
+          st_blk(w, x);
+        }
+        if (e == 0) st_blk(W + sB<S>(st.x, s), L);
+      }
+      if (e == 0) {
+        if (tk.z >= 0) {
+          if (se - tk.w > 1 && E > 1) wave_order<false>();
+          const Blk<T> Dk = ld_blk(W + sB<S>(tk.z, s));
+          const T det = Dk.a * Dk.d - Dk.b * Dk.c;
+          const T inv = recip(det);
+          const Blk<T> Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
+          const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
+          const bool zero = !(fabs(Dk.a) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
+                            !(fabs(det) > eps * fabs(Dk.a) * (fabs(Dk.c) + fabs(Dk.d))) ||
+                            !isfinite(inv);
+          if (zero) piv[s] = 1;
+          st_blk(c.dinv + sB<S>(a, s), Di);
+        }
+        if (fwd) { c.y[sP<S>(a, s)] = y0; c.y[sP<S>(a, s) + 1] = y1; }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// level-scheduled row solves with LDS-staged rows and columns: forward
+// (unit L, lower) or backward (U with inverted pivots)
+template <typename T, int S, bool LOWER>
+__device__ __forceinline__ void phase_solve_st(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin,
+                                               unsigned char* lds) {
+  const int nch = LOWER ? D.nch_fs : D.nch_bs;
+  const int* ptr = LOWER ? m.fs_ptr : m.bs_ptr;
+  const int* blob = LOWER ? m.fs_blob : m.bs_blob;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int* h = stage_chunk(ptr, blob, ch, lds, tid, nt);
+    const int nrow = h[0];
+    const int4* rw = reinterpret_cast<const int4*>(h + 4);
+    const int* cols = reinterpret_cast<const int*>(rw + nrow + 1);
+    const Grp g = groups(nrow, tid, nt, gmin);
+    const int G = g.G;
+    const int s = g.lane % S, e = g.lane / S, E = G / S;
+    for (int ri = g.gid; ri < nrow; ri += g.ng) {
+      const int4 r = rw[ri];   // row, first position, -, first column
+      const int a = r.x, n = rw[ri + 1].w - r.w;
+      T s0 = T(0), s1 = T(0);
+      for (int j = e; j < n; j += E) {
+        const Blk<T> M = ld_blk(c.lu + sB<S>(r.y + j, s));
+        const int k = cols[r.w + j];
+        const T z0 = c.y[sP<S>(k, s)], z1 = c.y[sP<S>(k, s) + 1];
+        s0 += M.a * z0 + M.b * z1;
+        s1 += M.c * z0 + M.d * z1;
+      }
+      s0 = group_sum<T, S>(s0, G);
+      s1 = group_sum<T, S>(s1, G);
+      if (e == 0) {
+        if (LOWER) {
+          c.y[sP<S>(a, s)] -= s0;
+          c.y[sP<S>(a, s) + 1] -= s1;
+        } else {
+          const Blk<T> Di = ld_blk(c.dinv + sB<S>(a, s));
+          const T t0 = c.y[sP<S>(a, s)] - s0, t1 = c.y[sP<S>(a, s) + 1] - s1;
+          c.y[sP<S>(a, s)] = Di.a * t0 + Di.b * t1;
+          c.y[sP<S>(a, s) + 1] = Di.c * t0 + Di.d * t1;
+        }
       }
     }
     __syncthreads();
@@ -1032,6 +1178,7 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
   const bool mixed = sizeof(T) == 4;
   const int gmin = kp.gmin > S ? kp.gmin : S;
   const int wv = tid >> 6, ln = tid & 63;   // LDS-resident tails: wavefront wv <-> scenario wv
+  unsigned char* stg = smem + kScratchBytes; // HBM-resident slices: staged level metadata
   TailRow<T> R;                             // this wavefront's factored tail rows
   while (true) {
     phase_mismatch<T, S>(m, D, c, tid, nt, scr);
@@ -1052,10 +1199,11 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
     if (!act) break;
     for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
     phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
-    phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, true, piv);
     if constexpr (RES) {
+      phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, true, piv);
       if (wv < S) rt_factor<T, S>(m, D, c, wv, ln, true, piv, R);
     } else {
+      phase_factor_st<T, S>(m, D, c, tid, nt, gmin, true, piv, stg);
       phase_tail_factor<T, S, RES>(m, D, c, tid, nt, true, piv);
     }
     __syncthreads();
@@ -1071,7 +1219,11 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
       phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
     }
     __syncthreads();
-    phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
+    if constexpr (RES) {
+      phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
+    } else {
+      phase_solve_st<T, S, false>(m, D, c, tid, nt, gmin, stg);
+    }
     for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
     __syncthreads();
     if (mixed) {
@@ -1089,7 +1241,11 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
           }
           if (!ref) break;
         }
-        phase_fsolve<T, S>(m, D, c, tid, nt, gmin);
+        if constexpr (RES) {
+          phase_fsolve<T, S>(m, D, c, tid, nt, gmin);
+        } else {
+          phase_solve_st<T, S, true>(m, D, c, tid, nt, gmin, stg);
+        }
         if constexpr (RES) {
           if (wv < S) {
             rt_fsolve<T, S>(m, D, c, wv, ln, R);
@@ -1101,7 +1257,11 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
           phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
         }
         __syncthreads();
-        phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
+        if constexpr (RES) {
+          phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
+        } else {
+          phase_solve_st<T, S, false>(m, D, c, tid, nt, gmin, stg);
+        }
         for (int q = tid; q < 2 * nb * S; q += nt)
           if ((ref >> ((q >> 1) % S)) & 1) c.dx[q] += double(c.y[q]);
         __syncthreads();
@@ -1161,7 +1321,11 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
   if (keep) {
     if (tid < S) piv[tid] = 0;
     phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
-    phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, false, piv);
+    if constexpr (RES) {
+      phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, false, piv);
+    } else {
+      phase_factor_st<T, S>(m, D, c, tid, nt, gmin, false, piv, stg);
+    }
     if constexpr (RES) {
       if (wv < S) {
         rt_factor<T, S>(m, D, c, wv, ln, false, piv, R);

@@ -40,6 +40,105 @@ int32_t find_sorted(const int32_t* first, const int32_t* last, int32_t key) {
 
 }  // namespace
 
+int build_level_chunks(const Symbolic& S, int32_t budget_ints, LevelChunks& out, std::string& err) {
+  out = LevelChunks{};
+  // generic chunker: items of one level are appended to the current chunk
+  // while it fits; emit() closes a chunk
+  struct Builder {
+    std::vector<int32_t>* ptr;
+    std::vector<int32_t>* blob;
+    int32_t max_ints = 0;
+    std::vector<int32_t> rec, rec2, tail;   // first and second record lists, payload
+    int32_t n1 = 0, n2 = 0;
+    void emit(const int32_t* hdr4, int32_t end1, int32_t end2) {
+      if (n1 == 0) return;
+      std::vector<int32_t> c(hdr4, hdr4 + 4);
+      c.insert(c.end(), rec.begin(), rec.end());
+      c.insert(c.end(), {0, 0, 0, end1});
+      if (!rec2.empty() || end2 >= 0) {
+        c.insert(c.end(), rec2.begin(), rec2.end());
+        c.insert(c.end(), {0, 0, 0, end2});
+      }
+      c.insert(c.end(), tail.begin(), tail.end());
+      while (c.size() % 4) c.push_back(0);
+      ptr->push_back((int32_t)blob->size());
+      blob->insert(blob->end(), c.begin(), c.end());
+      max_ints = std::max<int32_t>(max_ints, (int32_t)c.size());
+      rec.clear(); rec2.clear(); tail.clear(); n1 = n2 = 0;
+    }
+  };
+  const int32_t nb = S.nb, tb = S.tail_base;
+  // ---- factor
+  {
+    Builder B{&out.f_ptr, &out.f_blob};
+    for (int32_t h = 0; h < S.n_task_levels; ++h) {
+      for (int32_t ti = S.task_ptr[h]; ti < S.task_ptr[h + 1]; ++ti) {
+        const int32_t a = S.task4[4 * ti], sb = S.task4[4 * ti + 1], se = S.task4[4 * ti + 2];
+        const int32_t fin = S.task4[4 * ti + 3];
+        int32_t nt = 0;
+        for (int32_t i = sb; i < se; ++i) nt += S.step4[4 * i + 3];
+        const int32_t need = 4 + 4 * (B.n1 + 2) + 4 * (B.n2 + (se - sb) + 1) + (int32_t)B.tail.size() + nt + 3;
+        if (need > budget_ints && B.n1 > 0) {
+          const int32_t hdr[4] = {B.n1, B.n2, (int32_t)B.tail.size(), 0};
+          B.emit(hdr, B.n2, (int32_t)B.tail.size());
+        }
+        if (4 + 8 + 4 * ((se - sb) + 1) + nt + 3 > budget_ints) {
+          err = "template: a factor task exceeds the metadata chunk budget";
+          return -1;
+        }
+        B.rec.insert(B.rec.end(), {a, S.rp[a], fin ? S.diag[a] - S.rp[a] : -1, B.n2});
+        for (int32_t i = sb; i < se; ++i) {
+          const int32_t n = S.step4[4 * i + 3], ts = S.step_ts[i];
+          B.rec2.insert(B.rec2.end(), {S.step4[4 * i], S.step4[4 * i + 1], S.step4[4 * i + 2],
+                                       (int32_t)B.tail.size()});
+          for (int32_t t = 0; t < n; ++t) B.tail.push_back(S.upd_tgt[ts + t]);
+          B.n2++;
+        }
+        B.n1++;
+      }
+      const int32_t hdr[4] = {B.n1, B.n2, (int32_t)B.tail.size(), 0};
+      B.emit(hdr, B.n2, (int32_t)B.tail.size());
+    }
+    out.f_ptr.push_back((int32_t)out.f_blob.size());
+    out.max_ints = std::max(out.max_ints, B.max_ints);
+  }
+  // ---- solves: rows of a level with their column lists
+  auto solves = [&](const std::vector<int32_t>& lptr, const std::vector<int32_t>& lrows, int32_t nlev,
+                    bool lower, std::vector<int32_t>& ptr, std::vector<int32_t>& blob) -> int {
+    Builder B{&ptr, &blob};
+    for (int32_t h = 0; h < nlev; ++h) {
+      for (int32_t ri = lptr[h]; ri < lptr[h + 1]; ++ri) {
+        const int32_t a = lrows[ri];
+        const int32_t p0 = lower ? S.rp[a] : S.diag[a] + 1;
+        const int32_t p1 = lower ? S.diag[a] : S.rp[a + 1];
+        const int32_t need = 4 + 4 * (B.n1 + 2) + (int32_t)B.tail.size() + (p1 - p0) + 3;
+        if (need > budget_ints && B.n1 > 0) {
+          const int32_t hdr[4] = {B.n1, (int32_t)B.tail.size(), 0, 0};
+          B.emit(hdr, (int32_t)B.tail.size(), -1);
+        }
+        if (4 + 8 + (p1 - p0) + 3 > budget_ints) {
+          err = "template: a solve row exceeds the metadata chunk budget";
+          return -1;
+        }
+        B.rec.insert(B.rec.end(), {a, p0, 0, (int32_t)B.tail.size()});
+        for (int32_t p = p0; p < p1; ++p) B.tail.push_back(S.ci[p]);
+        B.n1++;
+      }
+      const int32_t hdr[4] = {B.n1, (int32_t)B.tail.size(), 0, 0};
+      B.emit(hdr, (int32_t)B.tail.size(), -1);
+    }
+    ptr.push_back((int32_t)blob.size());
+    out.max_ints = std::max(out.max_ints, B.max_ints);
+    return 0;
+  };
+  if (solves(S.lev_l_ptr, S.lev_l_rows, S.n_fs_levels, true, out.fs_ptr, out.fs_blob)) return -1;
+  if (solves(S.lev_um_ptr, S.lev_um_rows, (int32_t)S.lev_um_ptr.size() - 1, false, out.bs_ptr, out.bs_blob))
+    return -1;
+  (void)nb;
+  (void)tb;
+  return 0;
+}
+
 int ybus_from_branches(int32_t n_bus, int32_t n_branch, const int32_t* f, const int32_t* t,
                        const double* r, const double* x, const double* bc,
                        std::vector<int32_t>& rp, std::vector<int32_t>& ci,

@@ -97,6 +97,31 @@ struct Symbolic {
   int32_t n_levels_u() const { return (int32_t)lev_u_ptr.size() - 1; }
 };
 
+// Level schedules cut into chunks whose metadata a workgroup copies into LDS
+// before working through it (HBM-resident slices, where every dependent
+// metadata load would otherwise be an L2 round trip).  A chunk holds whole
+// tasks (rows) of one level; chunks follow level order; each chunk is a run
+// of int32 padded to a multiple of 4:
+//  factor:  [ntask, nstep, ntgt, 0], ntask + 1 task records {row, rp[row],
+//           diag[row] - rp[row] if the row inverts its pivot block else -1,
+//           first step}, nstep + 1 step records {L position - rp[row], pivot
+//           row, first position of the pivot's U row right of the diagonal,
+//           first target}, ntgt row-relative target positions;
+//  solves:  [nrow, ncol, 0, 0], nrow + 1 row records {row, first position,
+//           0, first column}, ncol column indices (forward: the L part of
+//           each row, backward: the U part right of the diagonal).
+// The trailing record of each list only carries the end index.
+struct LevelChunks {
+  std::vector<int32_t> f_ptr, f_blob;     // factor tasks
+  std::vector<int32_t> fs_ptr, fs_blob;   // forward solve, rows outside the tail
+  std::vector<int32_t> bs_ptr, bs_blob;   // backward solve, rows outside the tail
+  int32_t max_ints = 0;                   // largest chunk, int32 words
+};
+
+// budget_ints: largest chunk in int32 words.  Returns 0, or PF_EINVAL if a
+// single row does not fit the budget.
+int build_level_chunks(const Symbolic& S, int32_t budget_ints, LevelChunks& out, std::string& err);
+
 // Returns 0 on success; on failure a negative PF_E* code and a message.
 // tail_max: largest dense tail (0 disables it; at most 64)
 int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
