@@ -282,30 +282,32 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   }
   Packer pk;
   sable::SymOffsets& so = t->so;
+  // level metadata in chunks of whole rows: read in place from the LDS image
+  // by LDS-resident slices, staged chunk by chunk in LDS by HBM-resident ones
+  sable::LevelChunks chunks;
+  rc = sable::build_level_chunks(S, kChunkInts, chunks, err);
+  if (rc != 0) { delete t; return fail(PF_EINVAL, err); }
   so.bus_type = (int)pk.add(S.bus_type); so.bus_blk = (int)pk.add(S.bus_blk);
   so.y_rp = (int)pk.add(S.y_rp); so.y_ci = (int)pk.add(S.y_ci);
   so.y_g = (int)pk.add(S.y_g); so.y_b = (int)pk.add(S.y_b);
   so.rp = (int)pk.add(S.rp); so.ci = (int)pk.add(S.ci); so.diag = (int)pk.add(S.diag);
-  so.fill4 = (int)pk.add(S.fill4); so.task_ptr = (int)pk.add(S.task_ptr);
+  so.fill4 = (int)pk.add(S.fill4);
+  so.tail_pos = (int)pk.add(S.tail_pos); so.tail_split = (int)pk.add(S.tail_split);
+  so.tail_mask = (int)pk.add(S.tail_mask);
+  so.f_ptr = (int)pk.add(chunks.f_ptr); so.f_blob = (int)pk.add(chunks.f_blob);
+  so.fs_ptr = (int)pk.add(chunks.fs_ptr); so.fs_blob = (int)pk.add(chunks.fs_blob);
+  so.bs_ptr = (int)pk.add(chunks.bs_ptr); so.bs_blob = (int)pk.add(chunks.bs_blob);
+  so.newton_bytes = (int)pk.align();
+  so.task_ptr = (int)pk.add(S.task_ptr);
   so.task4 = (int)pk.add(S.task4); so.step4 = (int)pk.add(S.step4);
   so.step_ts = (int)pk.add(S.step_ts); so.upd_tgt = (int)pk.add(S.upd_tgt);
   so.lev_l_ptr = (int)pk.add(S.lev_l_ptr); so.lev_l_rows = (int)pk.add(S.lev_l_rows);
   so.lev_um_ptr = (int)pk.add(S.lev_um_ptr); so.lev_um_rows = (int)pk.add(S.lev_um_rows);
-  so.tail_pos = (int)pk.add(S.tail_pos); so.tail_split = (int)pk.add(S.tail_split);
   so.tk_ptr = (int)pk.add(S.tk_ptr); so.tstep4 = (int)pk.add(S.tstep4);
-  so.tail_mask = (int)pk.add(S.tail_mask);
-  so.newton_bytes = (int)pk.align();
   so.lev_u_ptr = (int)pk.add(S.lev_u_ptr); so.lev_u_rows = (int)pk.add(S.lev_u_rows);
   so.blk_bus = (int)pk.add(S.blk_bus); so.lu_src = (int)pk.add(S.lu_src);
   so.mirror = (int)pk.add(S.mirror); so.y_tr = (int)pk.add(S.y_tr);
   so.ord_p = (int)pk.add(ord_p); so.ord_q = (int)pk.add(ord_q);
-  // level metadata in chunks that HBM-resident workgroups stage in LDS
-  sable::LevelChunks chunks;
-  rc = sable::build_level_chunks(S, kChunkInts, chunks, err);
-  if (rc != 0) { delete t; return fail(PF_EINVAL, err); }
-  so.f_ptr = (int)pk.add(chunks.f_ptr); so.f_blob = (int)pk.add(chunks.f_blob);
-  so.fs_ptr = (int)pk.add(chunks.fs_ptr); so.fs_blob = (int)pk.add(chunks.fs_blob);
-  so.bs_ptr = (int)pk.add(chunks.bs_ptr); so.bs_blob = (int)pk.add(chunks.bs_blob);
   so.total_bytes = (int)pk.align();
   sable::Dims& dm = t->dims;
   dm.n_bus = S.n_bus; dm.nb = S.nb; dm.nnzb = S.nnzb(); dm.nj = S.nb + S.n_pq; dm.npq = S.n_pq;

@@ -38,13 +38,13 @@ static_assert(kFnvOff + 8 * kMaxSlice <= kScratchBytes, "scratch layout");
 // copied whole into LDS when the slice of a workgroup is LDS-resident).
 struct SymOffsets {
   int bus_type, bus_blk, y_rp, y_ci, y_g, y_b;
-  int rp, ci, diag, fill4, task_ptr, task4, step4, step_ts, upd_tgt;
-  int lev_l_ptr, lev_l_rows, lev_um_ptr, lev_um_rows, tail_pos, tail_split, tk_ptr, tstep4;
-  int tail_mask;
+  int rp, ci, diag, fill4, tail_pos, tail_split, tail_mask;
+  int f_ptr, f_blob, fs_ptr, fs_blob, bs_ptr, bs_blob;   // level metadata chunks
   int newton_bytes;
+  int task_ptr, task4, step4, step_ts, upd_tgt;
+  int lev_l_ptr, lev_l_rows, lev_um_ptr, lev_um_rows, tk_ptr, tstep4;
   int lev_u_ptr, lev_u_rows;
   int blk_bus, lu_src, mirror, y_tr, ord_p, ord_q;
-  int f_ptr, f_blob, fs_ptr, fs_blob, bs_ptr, bs_blob;   // level chunks staged in LDS (HBM slices)
   int total_bytes;
 };
 

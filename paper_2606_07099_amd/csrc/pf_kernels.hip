@@ -68,44 +68,45 @@ struct Sym {
 __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned char* g,
                                         const SymOffsets& o) {
   Sym m;
-  m.bus_type = reinterpret_cast<const int*>(nb + o.bus_type);
-  m.bus_blk = reinterpret_cast<const int*>(nb + o.bus_blk);
-  m.y_rp = reinterpret_cast<const int*>(nb + o.y_rp);
-  m.y_ci = reinterpret_cast<const int*>(nb + o.y_ci);
+  auto I = [](const unsigned char* b, int off) { return reinterpret_cast<const int*>(b + off); };
+  m.bus_type = I(nb, o.bus_type);
+  m.bus_blk = I(nb, o.bus_blk);
+  m.y_rp = I(nb, o.y_rp);
+  m.y_ci = I(nb, o.y_ci);
   m.y_g = reinterpret_cast<const double*>(nb + o.y_g);
   m.y_b = reinterpret_cast<const double*>(nb + o.y_b);
-  m.rp = reinterpret_cast<const int*>(nb + o.rp);
-  m.ci = reinterpret_cast<const int*>(nb + o.ci);
-  m.diag = reinterpret_cast<const int*>(nb + o.diag);
+  m.rp = I(nb, o.rp);
+  m.ci = I(nb, o.ci);
+  m.diag = I(nb, o.diag);
   m.fill4 = reinterpret_cast<const int4*>(nb + o.fill4);
-  m.task_ptr = reinterpret_cast<const int*>(nb + o.task_ptr);
-  m.task4 = reinterpret_cast<const int4*>(nb + o.task4);
-  m.step4 = reinterpret_cast<const int4*>(nb + o.step4);
-  m.step_ts = reinterpret_cast<const int*>(nb + o.step_ts);
-  m.upd_tgt = reinterpret_cast<const int*>(nb + o.upd_tgt);
-  m.lev_l_ptr = reinterpret_cast<const int*>(nb + o.lev_l_ptr);
-  m.lev_l_rows = reinterpret_cast<const int*>(nb + o.lev_l_rows);
-  m.lev_um_ptr = reinterpret_cast<const int*>(nb + o.lev_um_ptr);
-  m.lev_um_rows = reinterpret_cast<const int*>(nb + o.lev_um_rows);
-  m.tail_pos = reinterpret_cast<const int*>(nb + o.tail_pos);
-  m.tail_split = reinterpret_cast<const int*>(nb + o.tail_split);
-  m.tk_ptr = reinterpret_cast<const int*>(nb + o.tk_ptr);
-  m.tstep4 = reinterpret_cast<const int4*>(nb + o.tstep4);
+  m.tail_pos = I(nb, o.tail_pos);
+  m.tail_split = I(nb, o.tail_split);
   m.tail_mask = reinterpret_cast<const unsigned*>(nb + o.tail_mask);
-  m.lev_u_ptr = reinterpret_cast<const int*>(g + o.lev_u_ptr);
-  m.lev_u_rows = reinterpret_cast<const int*>(g + o.lev_u_rows);
-  m.blk_bus = reinterpret_cast<const int*>(g + o.blk_bus);
-  m.lu_src = reinterpret_cast<const int*>(g + o.lu_src);
-  m.mirror = reinterpret_cast<const int*>(g + o.mirror);
-  m.y_tr = reinterpret_cast<const int*>(g + o.y_tr);
-  m.ord_p = reinterpret_cast<const int*>(g + o.ord_p);
-  m.ord_q = reinterpret_cast<const int*>(g + o.ord_q);
-  m.f_ptr = reinterpret_cast<const int*>(g + o.f_ptr);
-  m.f_blob = reinterpret_cast<const int*>(g + o.f_blob);
-  m.fs_ptr = reinterpret_cast<const int*>(g + o.fs_ptr);
-  m.fs_blob = reinterpret_cast<const int*>(g + o.fs_blob);
-  m.bs_ptr = reinterpret_cast<const int*>(g + o.bs_ptr);
-  m.bs_blob = reinterpret_cast<const int*>(g + o.bs_blob);
+  m.f_ptr = I(nb, o.f_ptr);
+  m.f_blob = I(nb, o.f_blob);
+  m.fs_ptr = I(nb, o.fs_ptr);
+  m.fs_blob = I(nb, o.fs_blob);
+  m.bs_ptr = I(nb, o.bs_ptr);
+  m.bs_blob = I(nb, o.bs_blob);
+  m.task_ptr = I(g, o.task_ptr);
+  m.task4 = reinterpret_cast<const int4*>(g + o.task4);
+  m.step4 = reinterpret_cast<const int4*>(g + o.step4);
+  m.step_ts = I(g, o.step_ts);
+  m.upd_tgt = I(g, o.upd_tgt);
+  m.lev_l_ptr = I(g, o.lev_l_ptr);
+  m.lev_l_rows = I(g, o.lev_l_rows);
+  m.lev_um_ptr = I(g, o.lev_um_ptr);
+  m.lev_um_rows = I(g, o.lev_um_rows);
+  m.tk_ptr = I(g, o.tk_ptr);
+  m.tstep4 = reinterpret_cast<const int4*>(g + o.tstep4);
+  m.lev_u_ptr = I(g, o.lev_u_ptr);
+  m.lev_u_rows = I(g, o.lev_u_rows);
+  m.blk_bus = I(g, o.blk_bus);
+  m.lu_src = I(g, o.lu_src);
+  m.mirror = I(g, o.mirror);
+  m.y_tr = I(g, o.y_tr);
+  m.ord_p = I(g, o.ord_p);
+  m.ord_q = I(g, o.ord_q);
   return m;
 }
 
@@ -310,6 +311,26 @@ __device__ __forceinline__ void phase_fill(const Sym& m, const Dims& D, St<T>& c
   __syncthreads();
 }
 
+// ----------------------------------------------------------------------------
+// level-scheduled factor and solves.  HBM-resident slices first copy each
+// chunk of level metadata (tasks, steps, targets / rows, columns) into LDS
+// with the whole workgroup, so that only the value loads of a step reach HBM
+
+// metadata chunk c of a schedule: in place when the image is LDS-resident,
+// else copied into LDS by the whole workgroup; returns its base (int32)
+template <bool STAGE>
+__device__ __forceinline__ const int* stage_chunk(const int* ptr, const int* blob, int c, unsigned char* lds,
+                                                  int tid, int nt) {
+  const int b0 = ptr[c];
+  if (!STAGE) return blob + b0;
+  const int b1 = ptr[c + 1];
+  int4* dst = reinterpret_cast<int4*>(lds);
+  const int4* src = reinterpret_cast<const int4*>(blob + b0);
+  for (int q = tid; q < ((b1 - b0) >> 2); q += nt) dst[q] = src[q];
+  __syncthreads();
+  return reinterpret_cast<const int*>(lds);
+}
+
 // Block LU (unit block-lower L, block-upper U with full 2x2 pivots) on the
 // fixed pattern, right-looking by levels with owner-computes rows: at level h
 // every row with a pivot k finished at level h-1 applies
@@ -318,168 +339,16 @@ __device__ __forceinline__ void phase_fill(const Sym& m, const Dims& D, St<T>& c
 // in inverts its own pivot block.  A row's entry A_ak is final when step k
 // runs because every pivot that updates it sits at a lower level.  The G
 // lanes of a task share one row (lane = scenario + S * entry) and belong to
-// one wavefront, whose LDS operations complete in program order, so a value
-// one lane writes in one step is seen by every lane in the next.  W is the
-// row: in place in an LDS-resident slice, a staging copy in LDS otherwise.
+// one wavefront: LDS operations of a wavefront complete in program order;
+// in HBM a fence orders successive steps unless one lane per scenario owns
+// the task (then every target is written and re-read by that lane).  The
+// level metadata comes in chunks of whole rows (RES: in place in the LDS
+// image; else staged into LDS).
 template <typename T, int S, bool RES>
 __device__ __forceinline__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin,
-                             bool fwd, int* piv) {
-  for (int lev = 0; lev < D.nlev_f; ++lev) {
-    const int t0 = m.task_ptr[lev], t1 = m.task_ptr[lev + 1];
-    const Grp g = groups(t1 - t0, tid, nt, gmin);
-    const int s = g.lane % S, e = g.lane / S, E = g.G / S;
-    for (int ti = t0 + g.gid; ti < t1; ti += g.ng) {
-      const int4 tk = m.task4[ti];
-      const int a = tk.x;
-      const int rs = m.rp[a];
-      T* W = c.lu + sB<S>(rs, 0);
-      T y0 = T(0), y1 = T(0);
-      if (fwd) { y0 = c.y[sP<S>(a, s)]; y1 = c.y[sP<S>(a, s) + 1]; }
-      // with one lane per scenario (E == 1) every target of the task is
-      // written and re-read by the same lane, so HBM state needs no fence
-      for (int i = tk.y; i < tk.z; ++i) {
-        if (i > tk.y && E > 1) wave_order<RES>();   // the previous step's targets may feed this one
-        const int4 st = m.step4[i];   // q, k, start of U(k,>k), |U(k,>k)|
-        const int ts = m.step_ts[i];
-        const int k = st.y;
-        const Blk<T> L = mul(ld_blk(W + sB<S>(st.x, s)), ld_blk(c.dinv + sB<S>(k, s)));
-        if (fwd) {
-          const T yk0 = c.y[sP<S>(k, s)], yk1 = c.y[sP<S>(k, s) + 1];
-          y0 -= L.a * yk0 + L.b * yk1;
-          y1 -= L.c * yk0 + L.d * yk1;
-        }
-        // the targets of one step are distinct: NB at a time, loads first
-        constexpr int NB = 2;
-        int t = e;
-        for (; t + (NB - 1) * E < st.w; t += NB * E) {
-          Blk<T> U[NB], x[NB];
-          T* w[NB];
-#pragma unroll
-          for (int u = 0; u < NB; ++u) {
-            U[u] = ld_blk(c.lu + sB<S>(st.z + t + u * E, s));
-            w[u] = W + sB<S>(m.upd_tgt[ts + t + u * E], s);
-            x[u] = ld_blk(w[u]);
-          }
-#pragma unroll
-          for (int u = 0; u < NB; ++u) {
-            const Blk<T> LU = mul(L, U[u]);
-            x[u].a -= LU.a; x[u].b -= LU.b; x[u].c -= LU.c; x[u].d -= LU.d;
-            st_blk(w[u], x[u]);
-          }
-        }
-        for (; t < st.w; t += E) {
-          const Blk<T> U = ld_blk(c.lu + sB<S>(st.z + t, s));
-          T* w = W + sB<S>(m.upd_tgt[ts + t], s);
-          Blk<T> x = ld_blk(w);
-          const Blk<T> LU = mul(L, U);
-          x.a -= LU.a; x.b -= LU.b; x.c -= LU.c; x.d -= LU.d;
-          st_blk(w, x);
-        }
-        if (e == 0) st_blk(W + sB<S>(st.x, s), L);
-      }
-      if (e == 0) {
-        if (tk.w) {
-          if (tk.z - tk.y > 1 && E > 1) wave_order<RES>();
-          const Blk<T> Dk = ld_blk(W + sB<S>(m.diag[a] - rs, s));
-          const T det = Dk.a * Dk.d - Dk.b * Dk.c;
-          const T inv = recip(det);
-          const Blk<T> Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
-          // pivots of the block: a, then the Schur complement d - c b / a
-          // (|det / a| > eps (|c| + |d|) written without the division)
-          const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
-          const bool zero = !(fabs(Dk.a) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
-                            !(fabs(det) > eps * fabs(Dk.a) * (fabs(Dk.c) + fabs(Dk.d))) ||
-                            !isfinite(inv);
-          if (zero) piv[s] = 1;
-          st_blk(c.dinv + sB<S>(a, s), Di);
-        }
-        if (fwd) { c.y[sP<S>(a, s)] = y0; c.y[sP<S>(a, s) + 1] = y1; }
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// L y = y (unit block-lower, in place) by L-levels
-template <typename T, int S>
-__device__ __forceinline__ void phase_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
-  for (int lev = 0; lev < D.nlev_fs; ++lev) {
-    const int r0 = m.lev_l_ptr[lev], r1 = m.lev_l_ptr[lev + 1];
-    const Grp g = groups(r1 - r0, tid, nt, gmin);
-    const int G = g.G;
-    const int s = g.lane % S, e = g.lane / S, E = G / S;
-    for (int ri = r0 + g.gid; ri < r1; ri += g.ng) {
-      const int a = m.lev_l_rows[ri];
-      T s0 = T(0), s1 = T(0);
-      for (int p = m.rp[a] + e; p < m.diag[a]; p += E) {
-        const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
-        const int k = m.ci[p];
-        const T y0 = c.y[sP<S>(k, s)], y1 = c.y[sP<S>(k, s) + 1];
-        s0 += L.a * y0 + L.b * y1;
-        s1 += L.c * y0 + L.d * y1;
-      }
-      s0 = group_sum<T, S>(s0, G);
-      s1 = group_sum<T, S>(s1, G);
-      if (e == 0) { c.y[sP<S>(a, s)] -= s0; c.y[sP<S>(a, s) + 1] -= s1; }
-    }
-    __syncthreads();
-  }
-}
-
-// U x = y (block-upper with full diagonal blocks, in place) by U-levels, for
-// the rows outside the dense tail (whose unknowns are solved first)
-template <typename T, int S>
-__device__ __forceinline__ void phase_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
-  for (int lev = 0; lev < D.nlev_bs; ++lev) {
-    const int r0 = m.lev_um_ptr[lev], r1 = m.lev_um_ptr[lev + 1];
-    const Grp g = groups(r1 - r0, tid, nt, gmin);
-    const int G = g.G;
-    const int s = g.lane % S, e = g.lane / S, E = G / S;
-    for (int ri = r0 + g.gid; ri < r1; ri += g.ng) {
-      const int a = m.lev_um_rows[ri];
-      T s0 = T(0), s1 = T(0);
-      for (int p = m.diag[a] + 1 + e; p < m.rp[a + 1]; p += E) {
-        const Blk<T> U = ld_blk(c.lu + sB<S>(p, s));
-        const int j = m.ci[p];
-        const T x0 = c.y[sP<S>(j, s)], x1 = c.y[sP<S>(j, s) + 1];
-        s0 += U.a * x0 + U.b * x1;
-        s1 += U.c * x0 + U.d * x1;
-      }
-      s0 = group_sum<T, S>(s0, G);
-      s1 = group_sum<T, S>(s1, G);
-      if (e == 0) {
-        const Blk<T> Di = ld_blk(c.dinv + sB<S>(a, s));
-        const T t0 = c.y[sP<S>(a, s)] - s0, t1 = c.y[sP<S>(a, s) + 1] - s1;
-        c.y[sP<S>(a, s)] = Di.a * t0 + Di.b * t1;
-        c.y[sP<S>(a, s) + 1] = Di.c * t0 + Di.d * t1;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// ----------------------------------------------------------------------------
-// HBM-resident slices: the same level schedules with each level's metadata
-// (tasks, steps, targets / rows, columns) first copied into LDS by the whole
-// workgroup, so that only the value loads of a step reach HBM
-
-// copies metadata chunk c of a schedule into LDS; returns its base (int32)
-__device__ __forceinline__ const int* stage_chunk(const int* ptr, const int* blob, int c, unsigned char* lds,
-                                                  int tid, int nt) {
-  const int b0 = ptr[c], b1 = ptr[c + 1];
-  int4* dst = reinterpret_cast<int4*>(lds);
-  const int4* src = reinterpret_cast<const int4*>(blob + b0);
-  for (int q = tid; q < ((b1 - b0) >> 2); q += nt) dst[q] = src[q];
-  __syncthreads();
-  return reinterpret_cast<const int*>(lds);
-}
-
-// the right-looking task schedule of phase_factor, metadata from LDS chunks
-template <typename T, int S>
-__device__ __forceinline__ void phase_factor_st(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin,
-                                                bool fwd, int* piv, unsigned char* lds) {
+                                             bool fwd, int* piv, unsigned char* lds) {
   for (int ch = 0; ch < D.nch_f; ++ch) {
-    const int* h = stage_chunk(m.f_ptr, m.f_blob, ch, lds, tid, nt);
+    const int* h = stage_chunk<!RES>(m.f_ptr, m.f_blob, ch, lds, tid, nt);
     const int ntask = h[0], nstep = h[1];
     const int4* tk4 = reinterpret_cast<const int4*>(h + 4);
     const int4* st4 = tk4 + ntask + 1;
@@ -493,7 +362,7 @@ __device__ __forceinline__ void phase_factor_st(const Sym& m, const Dims& D, St<
       T y0 = T(0), y1 = T(0);
       if (fwd) { y0 = c.y[sP<S>(a, s)]; y1 = c.y[sP<S>(a, s) + 1]; }
       for (int i = tk.w; i < se; ++i) {
-        if (i > tk.w && E > 1) wave_order<false>();   // the previous step's targets may feed this one
+        if (i > tk.w && E > 1) wave_order<RES>();   // the previous step's targets may feed this one
         const int4 st = st4[i];   // q, k, first U position, first target
         const int n = st4[i + 1].w - st.w;
         const int k = st.y;
@@ -533,7 +402,7 @@ __device__ __forceinline__ void phase_factor_st(const Sym& m, const Dims& D, St<
       }
       if (e == 0) {
         if (tk.z >= 0) {
-          if (se - tk.w > 1 && E > 1) wave_order<false>();
+          if (se - tk.w > 1 && E > 1) wave_order<RES>();
           const Blk<T> Dk = ld_blk(W + sB<S>(tk.z, s));
           const T det = Dk.a * Dk.d - Dk.b * Dk.c;
           const T inv = recip(det);
@@ -552,16 +421,17 @@ __device__ __forceinline__ void phase_factor_st(const Sym& m, const Dims& D, St<
   }
 }
 
-// level-scheduled row solves with LDS-staged rows and columns: forward
-// (unit L, lower) or backward (U with inverted pivots)
-template <typename T, int S, bool LOWER>
-__device__ __forceinline__ void phase_solve_st(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin,
-                                               unsigned char* lds) {
+// level-scheduled row solves of the rows outside the dense tail, rows and
+// their columns from the metadata chunks: forward (unit block-lower L, in
+// place in y) or backward (U with the inverted pivot blocks)
+template <typename T, int S, bool RES, bool LOWER>
+__device__ __forceinline__ void phase_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin,
+                                            unsigned char* lds) {
   const int nch = LOWER ? D.nch_fs : D.nch_bs;
   const int* ptr = LOWER ? m.fs_ptr : m.bs_ptr;
   const int* blob = LOWER ? m.fs_blob : m.bs_blob;
   for (int ch = 0; ch < nch; ++ch) {
-    const int* h = stage_chunk(ptr, blob, ch, lds, tid, nt);
+    const int* h = stage_chunk<!RES>(ptr, blob, ch, lds, tid, nt);
     const int nrow = h[0];
     const int4* rw = reinterpret_cast<const int4*>(h + 4);
     const int* cols = reinterpret_cast<const int*>(rw + nrow + 1);
@@ -1199,11 +1069,10 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
     if (!act) break;
     for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
     phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
+    phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, true, piv, stg);
     if constexpr (RES) {
-      phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, true, piv);
       if (wv < S) rt_factor<T, S>(m, D, c, wv, ln, true, piv, R);
     } else {
-      phase_factor_st<T, S>(m, D, c, tid, nt, gmin, true, piv, stg);
       phase_tail_factor<T, S, RES>(m, D, c, tid, nt, true, piv);
     }
     __syncthreads();
@@ -1219,11 +1088,7 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
       phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
     }
     __syncthreads();
-    if constexpr (RES) {
-      phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
-    } else {
-      phase_solve_st<T, S, false>(m, D, c, tid, nt, gmin, stg);
-    }
+    phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg);
     for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
     __syncthreads();
     if (mixed) {
@@ -1241,11 +1106,7 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
           }
           if (!ref) break;
         }
-        if constexpr (RES) {
-          phase_fsolve<T, S>(m, D, c, tid, nt, gmin);
-        } else {
-          phase_solve_st<T, S, true>(m, D, c, tid, nt, gmin, stg);
-        }
+        phase_solve<T, S, RES, true>(m, D, c, tid, nt, gmin, stg);
         if constexpr (RES) {
           if (wv < S) {
             rt_fsolve<T, S>(m, D, c, wv, ln, R);
@@ -1257,11 +1118,7 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
           phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
         }
         __syncthreads();
-        if constexpr (RES) {
-          phase_bsolve<T, S>(m, D, c, tid, nt, gmin);
-        } else {
-          phase_solve_st<T, S, false>(m, D, c, tid, nt, gmin, stg);
-        }
+        phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg);
         for (int q = tid; q < 2 * nb * S; q += nt)
           if ((ref >> ((q >> 1) % S)) & 1) c.dx[q] += double(c.y[q]);
         __syncthreads();
@@ -1321,11 +1178,7 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
   if (keep) {
     if (tid < S) piv[tid] = 0;
     phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
-    if constexpr (RES) {
-      phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, false, piv);
-    } else {
-      phase_factor_st<T, S>(m, D, c, tid, nt, gmin, false, piv, stg);
-    }
+    phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, false, piv, stg);
     if constexpr (RES) {
       if (wv < S) {
         rt_factor<T, S>(m, D, c, wv, ln, false, piv, R);
