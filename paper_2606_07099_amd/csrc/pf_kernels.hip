@@ -670,65 +670,65 @@ __device__ __forceinline__ void phase_tail_bsolve(const Sym& m, const Dims& D, S
 
 // ----------------------------------------------------------------------------
 // register-resident dense tail (LDS-resident slices): wavefront w handles the
-// tail of scenario w, lane l < t holds tail row l as 2x2 blocks in registers
-// for the duration of one tail phase (L part left of the diagonal, the
-// inverted pivot block on it, U part right of it).  The row is a register
-// vector per block component, indexed with the wavefront-uniform column
-// (register-indexing mode, no scratch); pivot rows and solved unknowns reach
-// the other lanes by lane broadcast; the structure masks skip the updates of
+// tail of scenario w.  Lanes 2l and 2l + 1 hold the two scalar rows of tail
+// block row l (components a b, resp. c d, of every 2x2 block), as register
+// vectors indexed with the wavefront-uniform column (register-indexing mode,
+// no scratch): L part left of the diagonal, the inverted pivot block on it, U
+// part right of it.  Pivot blocks, U rows and solved unknowns reach the
+// other lanes by lane broadcast; the structure masks skip the updates of
 // structurally zero blocks.  Same arithmetic, in the same order, as the
 // sparse per-pivot elimination.
 
 // register capacity of the dense tail, in block rows (one 32-dword register
-// tuple per block component)
+// tuple per scalar-row half)
 template <typename T>
 constexpr int tail_cap() { return sizeof(T) == 4 ? 32 : 16; }
 
 template <typename T>
 struct TailRow {
   typedef T V __attribute__((ext_vector_type(tail_cap<T>())));
-  V a, b, c, d;
-  __device__ __forceinline__ Blk<T> get(int j) const { return {a[j], b[j], c[j], d[j]}; }
-  __device__ __forceinline__ void set(int j, const Blk<T>& x) { a[j] = x.a; b[j] = x.b; c[j] = x.c; d[j] = x.d; }
+  V p, q;   // this lane's scalar row of block j: (p[j], q[j])
 };
 
-template <typename T>
-__device__ __forceinline__ Blk<T> bcast_blk(const Blk<T>& x, int l) {
-  return {lane_bcast(x.a, l), lane_bcast(x.b, l), lane_bcast(x.c, l), lane_bcast(x.d, l)};
+// the partner lane's value (lanes 2l <-> 2l + 1) by a DPP quad permutation
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double pair_swap(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename T>
-__device__ __forceinline__ Blk<T> sel_blk(bool p, const Blk<T>& x, const Blk<T>& y) {
-  return {p ? x.a : y.a, p ? x.b : y.b, p ? x.c : y.c, p ? x.d : y.d};
-}
-
-// blocks (l, j) of the tail for j in [j0, j1) into R (zero elsewhere); the
-// pivot block (l, l) comes from the inverted pivots when inv_diag
+// this lane's scalar row of the tail blocks (l, j), j < t, into R
 template <typename T, int S>
-__device__ __forceinline__ void rt_load(const Sym& m, const Dims& D, const St<T>& c, int s, int l,
-                                        int j0, int j1, bool inv_diag, TailRow<T>& R) {
+__device__ __forceinline__ void rt_load(const Sym& m, const Dims& D, const St<T>& c, int s, int l, int h,
+                                        TailRow<T>& R) {
   R = TailRow<T>{};
-  const int t = D.tail_t, tb = D.tail_base;
-  const Blk<T> z = {T(0), T(0), T(0), T(0)};
+  const int t = D.tail_t;
   // eight columns at a time, their index and value loads issued together
   for (int jb = 0; jb < t; jb += 8) {
     int p[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int j = jb + u;
-      p[u] = -1;
-      if (j < t && l < t && j >= j0 && j < j1) p[u] = (inv_diag && j == l) ? -2 : m.tail_pos[l * t + j];
+      p[u] = (j < t && l < t) ? m.tail_pos[l * t + j] : -1;
     }
-    Blk<T> v[8];
+    T x0[8], x1[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      v[u] = z;
-      if (p[u] == -2) v[u] = ld_blk(c.dinv + sB<S>(tb + l, s));
-      else if (p[u] >= 0) v[u] = ld_blk(c.lu + sB<S>(p[u], s));
+      x0[u] = T(0);
+      x1[u] = T(0);
+      if (p[u] >= 0) {
+        const T* b = c.lu + sB<S>(p[u], s) + 2 * h;
+        x0[u] = b[0];
+        x1[u] = b[1];
+      }
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (jb + u < t) R.set(jb + u, v[u]);
+      if (jb + u < t) { R.p[jb + u] = x0[u]; R.q[jb + u] = x1[u]; }
   }
 }
 
@@ -736,55 +736,56 @@ __device__ __forceinline__ void rt_load(const Sym& m, const Dims& D, const St<T>
 // iteration; with fwd, the forward solve of the tail rows' right-hand sides
 // is fused in
 template <typename T, int S>
-__device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c, int s, int l, bool fwd,
+__device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c, int s, int ln, bool fwd,
                                           int* piv, TailRow<T>& R) {
   const int t = D.tail_t, tb = D.tail_base;
   if (t == 0) return;
-  rt_load<T, S>(m, D, c, s, l, 0, t, false, R);
-  T y0 = T(0), y1 = T(0);
-  if (fwd && l < t) { y0 = c.y[sP<S>(tb + l, s)]; y1 = c.y[sP<S>(tb + l, s) + 1]; }
+  const int l = ln >> 1, h = ln & 1;
+  rt_load<T, S>(m, D, c, s, l, h, R);
+  T y = T(0);   // component h of the right-hand side of row l
+  if (fwd && l < t) y = c.y[sP<S>(tb + l, s) + h];
   bool zero = false;
   for (int k = 0; k < t; ++k) {
-    const Blk<T> Ak = R.get(k);
-    const Blk<T> Dk = bcast_blk(Ak, k);
-    const T det = Dk.a * Dk.d - Dk.b * Dk.c;
+    const T xp = R.p[k], xq = R.q[k];
+    const T da = lane_bcast(xp, 2 * k), db = lane_bcast(xq, 2 * k);
+    const T dc = lane_bcast(xp, 2 * k + 1), dd = lane_bcast(xq, 2 * k + 1);
+    const T det = da * dd - db * dc;
     const T inv = recip(det);
-    const Blk<T> Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
+    const T ia = dd * inv, ib = -db * inv, ic = -dc * inv, id = da * inv;
     // pivots of the block: a, then the Schur complement d - c b / a
     const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
-    zero |= !(fabs(Dk.a) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
-            !(fabs(det) > eps * fabs(Dk.a) * (fabs(Dk.c) + fabs(Dk.d))) || !isfinite(inv);
+    zero |= !(fabs(da) > eps * (fabs(da) + fabs(db))) ||
+            !(fabs(det) > eps * fabs(da) * (fabs(dc) + fabs(dd))) || !isfinite(inv);
     const bool below = l > k && l < t;
-    const Blk<T> L = mul(Ak, Di);
-    R.set(k, sel_blk(below, L, sel_blk(l == k, Di, Ak)));
+    const T l0 = xp * ia + xq * ic, l1 = xp * ib + xq * id;   // row h of A_lk D_k^-1
+    R.p[k] = below ? l0 : (l == k ? (h ? ic : ia) : xp);
+    R.q[k] = below ? l1 : (l == k ? (h ? id : ib) : xq);
     if (fwd) {
-      const T yk0 = lane_bcast(y0, k), yk1 = lane_bcast(y1, k);
-      if (below) {
-        y0 -= L.a * yk0 + L.b * yk1;
-        y1 -= L.c * yk0 + L.d * yk1;
-      }
+      const T yk0 = lane_bcast(y, 2 * k), yk1 = lane_bcast(y, 2 * k + 1);
+      if (below) y -= l0 * yk0 + l1 * yk1;
     }
     unsigned mk = __builtin_amdgcn_readfirstlane(m.tail_mask[k]);
     while (mk) {
       const int j = __builtin_ctz(mk);
       mk &= mk - 1;
-      const Blk<T> X = R.get(j);
-      const Blk<T> U = bcast_blk(X, k);
-      const Blk<T> LU = mul(L, U);
-      const Blk<T> Y = {X.a - LU.a, X.b - LU.b, X.c - LU.c, X.d - LU.d};
-      R.set(j, sel_blk(below, Y, X));
+      const T zp = R.p[j], zq = R.q[j];
+      const T ua = lane_bcast(zp, 2 * k), ub = lane_bcast(zq, 2 * k);
+      const T uc = lane_bcast(zp, 2 * k + 1), ud = lane_bcast(zq, 2 * k + 1);
+      R.p[j] = below ? zp - (l0 * ua + l1 * uc) : zp;
+      R.q[j] = below ? zq - (l0 * ub + l1 * ud) : zq;
     }
   }
-  if (zero && l == 0) piv[s] = 1;
-  if (fwd && l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+  if (zero && ln == 0) piv[s] = 1;
+  if (fwd && l < t) c.y[sP<S>(tb + l, s) + h] = y;
 }
 
 // the tail factors back into the slice's storage (multipliers and U blocks
 // in place, inverted pivots to dinv), for the adjoint
 template <typename T, int S>
-__device__ __forceinline__ void rt_store(const Sym& m, const Dims& D, St<T>& c, int s, int l,
+__device__ __forceinline__ void rt_store(const Sym& m, const Dims& D, St<T>& c, int s, int ln,
                                          const TailRow<T>& R) {
   const int t = D.tail_t, tb = D.tail_base;
+  const int l = ln >> 1, h = ln & 1;
   for (int jb = 0; jb < t; jb += 8) {
     int p[8];
 #pragma unroll
@@ -796,9 +797,11 @@ __device__ __forceinline__ void rt_store(const Sym& m, const Dims& D, St<T>& c, 
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       if (jb + u < t) {
-        const Blk<T> X = R.get(jb + u);
-        if (p[u] == -2) st_blk(c.dinv + sB<S>(tb + l, s), X);
-        else if (p[u] >= 0) st_blk(c.lu + sB<S>(p[u], s), X);
+        const T xp = R.p[jb + u], xq = R.q[jb + u];
+        T* b = nullptr;
+        if (p[u] == -2) b = c.dinv + sB<S>(tb + l, s) + 2 * h;
+        else if (p[u] >= 0) b = c.lu + sB<S>(p[u], s) + 2 * h;
+        if (b) { b[0] = xp; b[1] = xq; }
       }
     }
   }
@@ -807,62 +810,54 @@ __device__ __forceinline__ void rt_store(const Sym& m, const Dims& D, St<T>& c, 
 // forward solve of the tail rows: their terms on rows outside the tail,
 // then the unit block-lower tail block
 template <typename T, int S>
-__device__ __forceinline__ void rt_fsolve(const Sym& m, const Dims& D, St<T>& c, int s, int l,
+__device__ __forceinline__ void rt_fsolve(const Sym& m, const Dims& D, St<T>& c, int s, int ln,
                                           const TailRow<T>& R) {
   const int t = D.tail_t, tb = D.tail_base;
   if (t == 0) return;
-  T y0 = T(0), y1 = T(0);
+  const int l = ln >> 1, h = ln & 1;
+  T y = T(0);
   if (l < t) {
     const int a = tb + l;
-    y0 = c.y[sP<S>(a, s)];
-    y1 = c.y[sP<S>(a, s) + 1];
+    y = c.y[sP<S>(a, s) + h];
     for (int p = m.rp[a]; p < m.tail_split[l]; ++p) {
-      const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
+      const T* b = c.lu + sB<S>(p, s) + 2 * h;
       const int k = m.ci[p];
-      const T z0 = c.y[sP<S>(k, s)], z1 = c.y[sP<S>(k, s) + 1];
-      y0 -= L.a * z0 + L.b * z1;
-      y1 -= L.c * z0 + L.d * z1;
+      y -= b[0] * c.y[sP<S>(k, s)] + b[1] * c.y[sP<S>(k, s) + 1];
     }
   }
   unsigned lm = __builtin_amdgcn_readfirstlane(m.tail_mask[t]);
   while (lm) {
     const int j = __builtin_ctz(lm);
     lm &= lm - 1;
-    const Blk<T> L = R.get(j);
-    const T yj0 = lane_bcast(y0, j), yj1 = lane_bcast(y1, j);
-    if (l > j && l < t) {
-      y0 -= L.a * yj0 + L.b * yj1;
-      y1 -= L.c * yj0 + L.d * yj1;
-    }
+    const T lp = R.p[j], lq = R.q[j];
+    const T yj0 = lane_bcast(y, 2 * j), yj1 = lane_bcast(y, 2 * j + 1);
+    if (l > j && l < t) y -= lp * yj0 + lq * yj1;
   }
-  if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+  if (l < t) c.y[sP<S>(tb + l, s) + h] = y;
 }
 
 // backward solve of the tail block, the last unknown first
 template <typename T, int S>
-__device__ __forceinline__ void rt_bsolve(const Sym& m, const Dims& D, St<T>& c, int s, int l,
+__device__ __forceinline__ void rt_bsolve(const Sym& m, const Dims& D, St<T>& c, int s, int ln,
                                           const TailRow<T>& R) {
   const int t = D.tail_t, tb = D.tail_base;
   if (t == 0) return;
-  T y0 = T(0), y1 = T(0);
-  if (l < t) { y0 = c.y[sP<S>(tb + l, s)]; y1 = c.y[sP<S>(tb + l, s) + 1]; }
+  const int l = ln >> 1, h = ln & 1;
+  T y = T(0);
+  if (l < t) y = c.y[sP<S>(tb + l, s) + h];
   const unsigned cm = __builtin_amdgcn_readfirstlane(m.tail_mask[t + 1]);
   for (int j = t - 1; j >= 0; --j) {
-    const Blk<T> X = R.get(j);
-    if (l == j) {
-      const T x0 = X.a * y0 + X.b * y1, x1 = X.c * y0 + X.d * y1;
-      y0 = x0;
-      y1 = x1;
-    }
+    const T xp = R.p[j], xq = R.q[j];
+    // x_j = D_j^-1 y_j on the two lanes of row j: row h of the inverse
+    // times both components (the partner lane holds the other one)
+    const T yo = pair_swap(y);
+    if (l == j) y = xp * (h ? yo : y) + xq * (h ? y : yo);
     if ((cm >> j) & 1u) {
-      const T xj0 = lane_bcast(y0, j), xj1 = lane_bcast(y1, j);
-      if (l < j) {
-        y0 -= X.a * xj0 + X.b * xj1;
-        y1 -= X.c * xj0 + X.d * xj1;
-      }
+      const T xj0 = lane_bcast(y, 2 * j), xj1 = lane_bcast(y, 2 * j + 1);
+      if (l < j) y -= xp * xj0 + xq * xj1;
     }
   }
-  if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+  if (l < t) c.y[sP<S>(tb + l, s) + h] = y;
 }
 
 // dV = V (d|V|/|V| + j dtheta) for the correction dx (slack: 0)
