@@ -30,6 +30,9 @@ struct pf_template {
   int device = 0;
   sable::StateLayout lay{};  // HBM workspace, per scenario
   sable::StateLayout llay{}; // inside an LDS-resident slice, per scenario
+  sable::StateLayout alay{}; // inside an LDS-resident adjoint slice, per scenario
+  int adj_slice = 0;         // > 0: LDS-resident adjoint slices of this width
+  size_t adj_lds = 0;
   sable::SymOffsets so{};
   sable::Dims dims{};
   void* d_sym = nullptr;
@@ -113,6 +116,25 @@ sable::StateLayout make_lds_layout(int n_bus, int nb, int nnzb, bool mixed) {
   return L;
 }
 
+// per-scenario layout inside an LDS-resident adjoint slice: the kept state
+// (e f |V|), the currents, the adjoint scratch and the factors
+sable::StateLayout make_adj_layout(int n_bus, int nb, int nnzb) {
+  sable::StateLayout L{};
+  int o = 0;
+  L.o_e = o; o += n_bus; L.o_f = o; o += n_bus; L.o_vm = o; o += n_bus;
+  L.o_ire = o; o += n_bus; L.o_iim = o; o += n_bus;
+  L.o_dvr = o; o += n_bus; L.o_dvi = o; o += n_bus; L.o_aux = o; o += n_bus;
+  L.o_F = o; o += 2 * nb; L.o_dx = o; o += 2 * nb;
+  L.o_va = L.o_ps = L.o_qs = L.o_rvm = 0;
+  L.sd = round_up(o, 2);
+  int t = 0;
+  L.o_y = t; t += 2 * nb;
+  L.o_lu = t; t += 4 * nnzb;
+  L.o_dinv = t; t += 4 * nb;
+  L.st = round_up(t, 4);
+  return L;
+}
+
 // packs int32 / double host arrays into one device buffer
 struct Packer {
   std::vector<unsigned char> buf;
@@ -160,6 +182,7 @@ sable::KParams base_params(const pf_template* t) {
   kp.sym = static_cast<const unsigned char*>(t->d_sym);
   kp.lay = t->lay;
   kp.llay = t->llay;
+  kp.alay = t->alay;
   kp.ws_d = t->ws_d;
   kp.ws_t = t->ws_t;
   kp.ws_i = t->ws_i;
@@ -298,6 +321,11 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   so.fs_ptr = (int)pk.add(chunks.fs_ptr); so.fs_blob = (int)pk.add(chunks.fs_blob);
   so.bs_ptr = (int)pk.add(chunks.bs_ptr); so.bs_blob = (int)pk.add(chunks.bs_blob);
   so.newton_bytes = (int)pk.align();
+  so.ut_ptr = (int)pk.add(chunks.ut_ptr); so.ut_blob = (int)pk.add(chunks.ut_blob);
+  so.lt_ptr = (int)pk.add(chunks.lt_ptr); so.lt_blob = (int)pk.add(chunks.lt_blob);
+  so.tt_ptr = (int)pk.add(chunks.tt_ptr); so.tt_pairs = (int)pk.add(chunks.tt_pairs);
+  so.y_tr = (int)pk.add(S.y_tr);
+  so.adj_bytes = (int)pk.align();
   so.task_ptr = (int)pk.add(S.task_ptr);
   so.task4 = (int)pk.add(S.task4); so.step4 = (int)pk.add(S.step4);
   so.step_ts = (int)pk.add(S.step_ts); so.upd_tgt = (int)pk.add(S.upd_tgt);
@@ -306,7 +334,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   so.tk_ptr = (int)pk.add(S.tk_ptr); so.tstep4 = (int)pk.add(S.tstep4);
   so.lev_u_ptr = (int)pk.add(S.lev_u_ptr); so.lev_u_rows = (int)pk.add(S.lev_u_rows);
   so.blk_bus = (int)pk.add(S.blk_bus); so.lu_src = (int)pk.add(S.lu_src);
-  so.mirror = (int)pk.add(S.mirror); so.y_tr = (int)pk.add(S.y_tr);
+  so.mirror = (int)pk.add(S.mirror);
   so.ord_p = (int)pk.add(ord_p); so.ord_q = (int)pk.add(ord_q);
   so.total_bytes = (int)pk.align();
   sable::Dims& dm = t->dims;
@@ -319,6 +347,8 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   dm.nch_fs = (int)chunks.fs_ptr.size() - 1;
   dm.nch_bs = (int)chunks.bs_ptr.size() - 1;
   dm.chunk_ints = chunks.max_ints;
+  dm.nch_ut = (int)chunks.ut_ptr.size() - 1;
+  dm.nch_lt = (int)chunks.lt_ptr.size() - 1;
 
   // ---- launch shape: LDS-resident slices of S <= 4 scenarios (256 threads,
   // one wavefront per scenario's register-resident tail) when they fit,
@@ -341,6 +371,17 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   int nt = opt.block_threads;
   t->wstride = 0;
   t->gmin = 4;
+  // the adjoint: LDS-resident slices (256 threads, the tail in registers)
+  // whenever the Newton slices are, as wide as fits
+  t->alay = make_adj_layout(S.n_bus, S.nb, S.nnzb());
+  const size_t per_adj = 8 * (size_t)t->alay.sd + tsz * (size_t)t->alay.st;
+  t->adj_slice = 0;
+  if (best_s > 0) {
+    for (int sl : {4, 2, 1}) {
+      const size_t need = sable::kScratchBytes + (size_t)so.adj_bytes + sl * per_adj;
+      if (need <= max_lds) { t->adj_slice = sl; t->adj_lds = need; break; }
+    }
+  }
   if (best_s > 0) {
     t->lds_res = true;
     t->slice = best_s;
@@ -385,7 +426,8 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     bsl = sd + stt;
   }
   he = hipMemset(t->ws_i, 0xff, bi);
-  if (he == hipSuccess && t->lds_bytes > 64 * 1024) he = sable::set_lds_limits(t->lds_bytes);
+  if (he == hipSuccess && std::max(t->lds_bytes, t->adj_lds) > 64 * 1024)
+    he = sable::set_lds_limits(std::max(t->lds_bytes, t->adj_lds));
   if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he != hipSuccess) { pf_template_destroy(t); return hip_fail(he, "pf_template_build: set-up"); }
   t->ws_bytes = pk.buf.size() + bd + bt + bi + bsl;
@@ -453,7 +495,9 @@ int pf_adjoint_batch(pf_template* t, const double* g_vm, const double* g_va, dou
   kp.mode = sable::MODE_SOLVE;
   kp.g_vm = g_vm; kp.g_va = g_va;
   kp.g_pd = g_pd; kp.g_qd = g_qd; kp.g_pg = g_pg; kp.g_vset = g_vset;
-  hipError_t he = sable::launch_adjoint(kp, t->fp32, t->batch, t->nt, static_cast<hipStream_t>(hip_stream));
+  const int agrid = t->adj_slice ? (t->batch + t->adj_slice - 1) / t->adj_slice : t->batch;
+  hipError_t he = sable::launch_adjoint(kp, t->fp32, t->adj_slice, agrid, t->adj_slice ? sable::kResThreads : t->nt,
+                                        t->adj_lds, static_cast<hipStream_t>(hip_stream));
   if (he != hipSuccess) return hip_fail(he, "pf_adjoint_batch: launch");
   return PF_OK;
 }
@@ -491,7 +535,9 @@ int pf_eval_batch(pf_template* t, int32_t mode, int32_t count, const double* pd,
       he = sable::launch_newton(kp, t->fp32, t->slice, grid, t->nt, t->lds_bytes, t->lds_res, st);
       if (he == hipSuccess) {
         kp.mode = sable::MODE_EVAL_ADJOINT;
-        he = sable::launch_adjoint(kp, t->fp32, count, t->nt, st);
+        he = sable::launch_adjoint(kp, t->fp32, t->adj_slice,
+                                   t->adj_slice ? (count + t->adj_slice - 1) / t->adj_slice : count,
+                                   t->adj_slice ? sable::kResThreads : t->nt, t->adj_lds, st);
       }
       break;
     default:

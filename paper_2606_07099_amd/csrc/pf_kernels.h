@@ -41,10 +41,13 @@ struct SymOffsets {
   int rp, ci, diag, fill4, tail_pos, tail_split, tail_mask;
   int f_ptr, f_blob, fs_ptr, fs_blob, bs_ptr, bs_blob;   // level metadata chunks
   int newton_bytes;
+  // [newton_bytes, adj_bytes): what the LDS-resident adjoint reads besides
+  int ut_ptr, ut_blob, lt_ptr, lt_blob, tt_ptr, tt_pairs, y_tr;
+  int adj_bytes;
   int task_ptr, task4, step4, step_ts, upd_tgt;
   int lev_l_ptr, lev_l_rows, lev_um_ptr, lev_um_rows, tk_ptr, tstep4;
   int lev_u_ptr, lev_u_rows;
-  int blk_bus, lu_src, mirror, y_tr, ord_p, ord_q;
+  int blk_bus, lu_src, mirror, ord_p, ord_q;
   int total_bytes;
 };
 
@@ -54,6 +57,7 @@ struct Dims {
   int nlev_f, nlev_fs, nlev_bs;   // factor-task, forward and backward levels outside the tail
   int tail_t, tail_base;          // dense tail rows [tail_base, tail_base + tail_t)
   int nch_f, nch_fs, nch_bs;      // metadata chunks of the factor, forward and backward levels
+  int nch_ut, nch_lt;             // metadata chunks of the transposed solves
   int chunk_ints;                 // largest chunk (int32 words), staged after the LDS scratch
 };
 
@@ -75,6 +79,7 @@ struct KParams {
   const unsigned char* sym;  // packed symbolic image (device)
   StateLayout lay;           // per-scenario layout of the HBM workspace
   StateLayout llay;          // per-scenario layout inside an LDS-resident slice
+  StateLayout alay;          // per-scenario layout inside an LDS-resident adjoint slice
   double* ws_d;              // per-scenario workspace (layout lay)
   void* ws_t;
   int* ws_i;
@@ -95,7 +100,9 @@ constexpr int kResMaxSlice = 4;
 // slice = scenarios per workgroup: 1, 2 or 4 when LDS-resident, up to 16 otherwise.
 hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds,
                          bool lds_res, hipStream_t st);
-hipError_t launch_adjoint(const KParams& kp, bool fp32, int grid, int nt, hipStream_t st);
+// slice > 0: LDS-resident adjoint slices of that width (256 threads), else
+// one scenario per workgroup with HBM-resident factors
+hipError_t launch_adjoint(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds, hipStream_t st);
 hipError_t launch_jacobian_dense(const KParams& kp, int grid, hipStream_t st);
 hipError_t set_lds_limits(size_t max_lds);
 

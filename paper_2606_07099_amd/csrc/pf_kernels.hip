@@ -104,7 +104,7 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
   m.blk_bus = I(g, o.blk_bus);
   m.lu_src = I(g, o.lu_src);
   m.mirror = I(g, o.mirror);
-  m.y_tr = I(g, o.y_tr);
+  m.y_tr = I(g, o.y_tr);   // LDS-resident adjoint slices rebind it to their LDS copy
   m.ord_p = I(g, o.ord_p);
   m.ord_q = I(g, o.ord_q);
   return m;
@@ -1302,6 +1302,312 @@ __global__ void __launch_bounds__(1024) k_adjoint(KParams kp) {
 }
 
 // ----------------------------------------------------------------------------
+// LDS-resident adjoint slices (small grids): S scenarios per workgroup, the
+// kept state and factors copied into LDS, level metadata chunks in place in
+// the LDS image, the transposed dense tail in registers.  Same arithmetic as
+// k_adjoint.
+
+// metadata of the transposed solves
+struct AdjSym {
+  const int *ut_ptr, *ut_blob, *lt_ptr, *lt_blob, *tt_ptr, *tt_pairs;
+};
+
+__device__ __forceinline__ AdjSym bind_adj(const unsigned char* b, const SymOffsets& o) {
+  auto I = [](const unsigned char* x, int off) { return reinterpret_cast<const int*>(x + off); };
+  return {I(b, o.ut_ptr), I(b, o.ut_blob), I(b, o.lt_ptr), I(b, o.lt_blob), I(b, o.tt_ptr), I(b, o.tt_pairs)};
+}
+
+// U^T w = g by forward levels (UT) or L^T l = w by backward levels, rows
+// outside the tail, in place in y; entries are (column, position of the
+// transposed block) pairs
+template <typename T, int S, bool UT>
+__device__ __forceinline__ void phase_tsolve(const AdjSym& a, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
+  const int nch = UT ? D.nch_ut : D.nch_lt;
+  const int* ptr = UT ? a.ut_ptr : a.lt_ptr;
+  const int* blob = UT ? a.ut_blob : a.lt_blob;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int* h = blob + ptr[ch];
+    const int nrow = h[0];
+    const int4* rw = reinterpret_cast<const int4*>(h + 4);
+    const int* cols = reinterpret_cast<const int*>(rw + nrow + 1);
+    const Grp g = groups(nrow, tid, nt, gmin);
+    const int G = g.G;
+    const int s = g.lane % S, e = g.lane / S, E = G / S;
+    for (int ri = g.gid; ri < nrow; ri += g.ng) {
+      const int4 r = rw[ri];   // row, -, -, first pair
+      const int row = r.x, n = rw[ri + 1].w - r.w;
+      T s0 = T(0), s1 = T(0);
+      for (int j = e; j < n; j += E) {
+        const int k = cols[2 * (r.w + j)], mp = cols[2 * (r.w + j) + 1];
+        const Blk<T> B = ld_blk(c.lu + sB<S>(mp, s));
+        const T z0 = c.y[sP<S>(k, s)], z1 = c.y[sP<S>(k, s) + 1];
+        s0 += B.a * z0 + B.c * z1;
+        s1 += B.b * z0 + B.d * z1;
+      }
+      s0 = group_sum<T, S>(s0, G);
+      s1 = group_sum<T, S>(s1, G);
+      if (e == 0) {
+        if (UT) {
+          const Blk<T> Di = ld_blk(c.dinv + sB<S>(row, s));
+          const T t0 = c.y[sP<S>(row, s)] - s0, t1 = c.y[sP<S>(row, s) + 1] - s1;
+          c.y[sP<S>(row, s)] = Di.a * t0 + Di.c * t1;
+          c.y[sP<S>(row, s) + 1] = Di.b * t0 + Di.d * t1;
+        } else {
+          c.y[sP<S>(row, s)] -= s0;
+          c.y[sP<S>(row, s) + 1] -= s1;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// transposed solves of the tail rows, one wavefront per scenario, lanes 2l
+// and 2l + 1 = the two scalar rows of tail row l: lane row h of block j is
+// column h of the stored block (j, l) (U_jl^T left of the diagonal, the
+// transposed inverted pivot on it, L_jl^T right of it).  U^T forward (after
+// the terms on rows outside the tail), then L^T backward.
+template <typename T, int S>
+__device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const Dims& D, St<T>& c, int s, int ln) {
+  const int t = D.tail_t, tb = D.tail_base;
+  if (t == 0) return;
+  const int l = ln >> 1, h = ln & 1;
+  TailRow<T> R = TailRow<T>{};
+  for (int jb = 0; jb < t; jb += 8) {
+    int p[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = jb + u;
+      p[u] = -1;
+      if (j < t && l < t) p[u] = j == l ? -2 : m.tail_pos[j * t + l];
+    }
+    T x0[8], x1[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x0[u] = T(0);
+      x1[u] = T(0);
+      const T* b = p[u] == -2 ? c.dinv + sB<S>(tb + l, s) : (p[u] >= 0 ? c.lu + sB<S>(p[u], s) : nullptr);
+      if (b) { x0[u] = b[h]; x1[u] = b[2 + h]; }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (jb + u < t) { R.p[jb + u] = x0[u]; R.q[jb + u] = x1[u]; }
+  }
+  T y = T(0);
+  if (l < t) {
+    const int row = tb + l;
+    y = c.y[sP<S>(row, s) + h];
+    for (int q = a.tt_ptr[l]; q < a.tt_ptr[l + 1]; ++q) {
+      const int k = a.tt_pairs[2 * q], mp = a.tt_pairs[2 * q + 1];
+      const T* b = c.lu + sB<S>(mp, s);
+      y -= b[h] * c.y[sP<S>(k, s)] + b[2 + h] * c.y[sP<S>(k, s) + 1];
+    }
+  }
+  const unsigned lm = __builtin_amdgcn_readfirstlane(m.tail_mask[t]);
+  const unsigned cm = __builtin_amdgcn_readfirstlane(m.tail_mask[t + 1]);
+  for (int j = 0; j < t; ++j) {   // U^T w = g
+    const T xp = R.p[j], xq = R.q[j];
+    const T yo = pair_swap(y);
+    if (l == j) y = xp * (h ? yo : y) + xq * (h ? y : yo);
+    if ((lm >> j) & 1u) {
+      const T w0 = lane_bcast(y, 2 * j), w1 = lane_bcast(y, 2 * j + 1);
+      if (l > j && l < t) y -= xp * w0 + xq * w1;
+    }
+  }
+  for (int j = t - 1; j >= 0; --j) {   // L^T lambda = w
+    if ((cm >> j) & 1u) {
+      const T xp = R.p[j], xq = R.q[j];
+      const T z0 = lane_bcast(y, 2 * j), z1 = lane_bcast(y, 2 * j + 1);
+      if (l < j) y -= xp * z0 + xq * z1;
+    }
+  }
+  if (l < t) c.y[sP<S>(tb + l, s) + h] = y;
+}
+
+// the adjoint residual g - J1^T lam (and -(J3^T lam) in aux) on an interleaved
+// slice: as phase_adj_residual
+template <typename T, int S>
+__device__ __forceinline__ void phase_adj_residual_s(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
+                                                     const double* lam, const double* g, bool to_y) {
+  for (int idx = tid; idx < D.n_bus * S; idx += nt) {   // w_i = nu_i conj(V_i)
+    const int i = idx / S, s = idx % S;
+    const int a = m.bus_blk[i];
+    double nr = 0.0, ni = 0.0;
+    if (a >= 0) { nr = lam[sP<S>(a, s)]; ni = m.bus_type[i] == 0 ? lam[sP<S>(a, s) + 1] : 0.0; }
+    c.dvr[idx] = nr * c.e[idx] + ni * c.f[idx];
+    c.dvi[idx] = ni * c.e[idx] - nr * c.f[idx];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < D.n_bus * S; idx += nt) {
+    const int mb = idx / S, s = idx % S;
+    double tr = 0.0, ti = 0.0;
+    for (int q = m.y_rp[mb]; q < m.y_rp[mb + 1]; ++q) {
+      const int i = sI<S>(m.y_ci[q], s);
+      const int qt = m.y_tr[q];              // position of Y_im
+      const double yg = m.y_g[qt], yb = m.y_b[qt];
+      tr += yg * c.dvr[i] - yb * c.dvi[i];
+      ti += yg * c.dvi[i] + yb * c.dvr[i];
+    }
+    const int a = m.bus_blk[mb];
+    double nr = 0.0, ni = 0.0;
+    if (a >= 0) { nr = lam[sP<S>(a, s)]; ni = m.bus_type[mb] == 0 ? lam[sP<S>(a, s) + 1] : 0.0; }
+    const double ir = c.ire[idx], ii = c.iim[idx];
+    const double cr = (nr * ir - ni * ii) + tr;      // Re c_m
+    const double ci = -(nr * ii + ni * ir) + ti;     // Im c_m
+    const double e = c.e[idx], f = c.f[idx];
+    const double vcr = e * cr - f * ci;               // Re(V_m c_m)
+    const double vci = e * ci + f * cr;               // Im(V_m c_m)
+    c.aux[idx] = vcr / c.vm[idx];
+    if (a >= 0 && g) {
+      const double r0 = g[sP<S>(a, s)] - vci;
+      const double r1 = m.bus_type[mb] == 0 ? g[sP<S>(a, s) + 1] + vcr / c.vm[idx] : 0.0;
+      if (to_y) { c.y[sP<S>(a, s)] = T(r0); c.y[sP<S>(a, s) + 1] = T(r1); }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int S>
+__global__ void __launch_bounds__(kResThreads) k_adjoint_res(KParams kp) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int slice = blockIdx.x;
+  const Dims& D = kp.dims;
+  int* s_ok = reinterpret_cast<int*>(smem + kPivOff);
+  {   // the shared image prefix (Newton arrays, then the adjoint's), 16 bytes per lane
+    int4* dst = reinterpret_cast<int4*>(smem + kScratchBytes);
+    const int4* src = reinterpret_cast<const int4*>(kp.sym);
+    for (int q = tid; q < (kp.so.adj_bytes >> 4); q += nt) dst[q] = src[q];
+  }
+  const unsigned char* img = smem + kScratchBytes;
+  Sym m = bind_sym(img, kp.sym, kp.so);
+  m.y_tr = reinterpret_cast<const int*>(img + kp.so.y_tr);
+  const AdjSym as = bind_adj(img, kp.so);
+  double* dbase = reinterpret_cast<double*>(smem + kScratchBytes + kp.so.adj_bytes);
+  St<T> c = bind_state<T, S>(dbase, reinterpret_cast<T*>(dbase + (size_t)kp.alay.sd * S), kp.alay);
+  const int n = D.n_bus, nb = D.nb;
+  const bool eval = kp.mode == MODE_EVAL_ADJOINT;
+  const int wv = tid >> 6, ln = tid & 63;
+
+  // kept state and factors of the slice's scenarios (padding scenarios: flat, identity)
+  for (int idx = tid; idx < n * S; idx += nt) {
+    const int i = idx / S, s = idx % S;
+    const int b = slice * S + s;
+    double e = 1.0, f = 0.0, v = 1.0;
+    if (b < kp.count) {
+      const double* gd = kp.ws_d + (size_t)b * kp.lay.sd;
+      e = gd[kp.lay.o_e + i];
+      f = gd[kp.lay.o_f + i];
+      v = gd[kp.lay.o_vm + i];
+    }
+    c.e[idx] = e;
+    c.f[idx] = f;
+    c.vm[idx] = v;
+  }
+  for (int q = tid; q < 4 * D.nnzb * S; q += nt) {
+    const int comp = q & 3, blk = q >> 2, p = blk / S, s = blk % S;
+    const int b = slice * S + s;
+    c.lu[q] = b < kp.count ? reinterpret_cast<const T*>(kp.ws_t)[(size_t)b * kp.lay.st + kp.lay.o_lu + 4 * p + comp]
+                           : T(0);
+  }
+  for (int q = tid; q < 4 * nb * S; q += nt) {
+    const int comp = q & 3, blk = q >> 2, p = blk / S, s = blk % S;
+    const int b = slice * S + s;
+    c.dinv[q] = b < kp.count ? reinterpret_cast<const T*>(kp.ws_t)[(size_t)b * kp.lay.st + kp.lay.o_dinv + 4 * p + comp]
+                             : ((comp == 0 || comp == 3) ? T(1) : T(0));
+  }
+  if (tid < S) {
+    const int b = slice * S + tid;
+    s_ok[tid] = b < kp.count && kp.ws_i[(size_t)b * 4] == 0;
+  }
+  __syncthreads();
+  // I at the kept state, g_z1 per block into F
+  for (int idx = tid; idx < n * S; idx += nt) {
+    const int i = idx / S, s = idx % S;
+    const int b = slice * S + s;
+    double ir = 0.0, ii = 0.0;
+    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
+      const int j = sI<S>(m.y_ci[q], s);
+      ir += m.y_g[q] * c.e[j] - m.y_b[q] * c.f[j];
+      ii += m.y_g[q] * c.f[j] + m.y_b[q] * c.e[j];
+    }
+    c.ire[idx] = ir;
+    c.iim[idx] = ii;
+    const int a = m.bus_blk[i];
+    if (a < 0) continue;
+    double g0 = 0.0, g1 = 0.0;
+    if (b < kp.count) {
+      if (eval) {
+        const double* rhs = kp.rhs + (size_t)b * D.nj;
+        g0 = rhs[D.npq + m.ord_p[i]];
+        g1 = m.bus_type[i] == 0 ? rhs[m.ord_q[i]] : 0.0;
+      } else {
+        g0 = kp.g_va[(size_t)b * n + i];
+        g1 = m.bus_type[i] == 0 ? kp.g_vm[(size_t)b * n + i] : 0.0;
+      }
+    }
+    c.F[sP<S>(a, s)] = g0;
+    c.F[sP<S>(a, s) + 1] = g1;
+  }
+  __syncthreads();
+  for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(c.F[q]);
+  __syncthreads();
+  const int gmin = S > 4 ? S : 4;
+  auto solve = [&]() {
+    phase_tsolve<T, S, true>(as, D, c, tid, nt, gmin);
+    if (wv < S) rt_tsolve<T, S>(m, as, D, c, wv, ln);
+    __syncthreads();
+    phase_tsolve<T, S, false>(as, D, c, tid, nt, gmin);
+  };
+  solve();
+  for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
+  __syncthreads();
+  if (sizeof(T) == 4) {
+    for (int r = 0; r < kp.refine; ++r) {
+      phase_adj_residual_s<T, S>(m, D, c, tid, nt, c.dx, c.F, true);
+      solve();
+      for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] += double(c.y[q]);
+      __syncthreads();
+    }
+  }
+  if (eval) {
+    for (int idx = tid; idx < n * S; idx += nt) {
+      const int i = idx / S, s = idx % S;
+      const int b = slice * S + s;
+      const int a = m.bus_blk[i];
+      if (b >= kp.count || a < 0) continue;
+      double* o = kp.out + (size_t)b * D.nj;
+      o[m.ord_p[i]] = c.dx[sP<S>(a, s)];
+      if (m.bus_type[i] == 0) o[D.npvpq + m.ord_q[i]] = c.dx[sP<S>(a, s) + 1];
+    }
+    return;
+  }
+  // J3^T lam via the transposed product at the solution (-(J3^T lam) lands in aux)
+  phase_adj_residual_s<T, S>(m, D, c, tid, nt, c.dx, nullptr, false);
+  for (int idx = tid; idx < n * S; idx += nt) {
+    const int i = idx / S, s = idx % S;
+    const int b = slice * S + s;
+    if (b >= kp.count) continue;
+    const size_t o = (size_t)b * n + i;
+    const int a = m.bus_blk[i];
+    const int bt = m.bus_type[i];
+    double gpd = 0.0, gqd = 0.0, gpg = 0.0, gvs = 0.0;
+    if (s_ok[s]) {
+      if (a >= 0) {
+        gpd = c.dx[sP<S>(a, s)];
+        if (bt == 0) gqd = c.dx[sP<S>(a, s) + 1];
+        if (bt == 1) gpg = -c.dx[sP<S>(a, s)];
+      }
+      if (bt != 0) gvs = kp.g_vm[o] + c.aux[idx];
+    }
+    if (kp.g_pd) kp.g_pd[o] = gpd;
+    if (kp.g_qd) kp.g_qd[o] = gqd;
+    if (kp.g_pg) kp.g_pg[o] = gpg;
+    if (kp.g_vset) kp.g_vset[o] = gvs;
+  }
+}
+
+// ----------------------------------------------------------------------------
 // dense J1 export in the paper's ordering (evaluation entry point)
 
 __global__ void __launch_bounds__(256) k_jacobian_dense(KParams kp) {
@@ -1390,13 +1696,25 @@ hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int 
               : launch_newton_t<double>(kp, slice, grid, nt, lds, lds_res, st);
 }
 
-hipError_t launch_adjoint(const KParams& kp, bool fp32, int grid, int nt, hipStream_t st) {
-  if (fp32) {
-    hipLaunchKernelGGL((k_adjoint<float>), dim3(grid), dim3(nt), 0, st, kp);
-  } else {
-    hipLaunchKernelGGL((k_adjoint<double>), dim3(grid), dim3(nt), 0, st, kp);
+template <typename T>
+static hipError_t launch_adjoint_t(const KParams& kp, int slice, int grid, int nt, size_t lds, hipStream_t st) {
+  if (slice == 0) {
+    hipLaunchKernelGGL((k_adjoint<T>), dim3(grid), dim3(nt), 0, st, kp);
+    return hipGetLastError();
+  }
+  if (nt != kResThreads) return hipErrorInvalidValue;
+  switch (slice) {
+    case 1: hipLaunchKernelGGL((k_adjoint_res<T, 1>), dim3(grid), dim3(nt), lds, st, kp); break;
+    case 2: hipLaunchKernelGGL((k_adjoint_res<T, 2>), dim3(grid), dim3(nt), lds, st, kp); break;
+    case 4: hipLaunchKernelGGL((k_adjoint_res<T, 4>), dim3(grid), dim3(nt), lds, st, kp); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds, hipStream_t st) {
+  return fp32 ? launch_adjoint_t<float>(kp, slice, grid, nt, lds, st)
+              : launch_adjoint_t<double>(kp, slice, grid, nt, lds, st);
 }
 
 hipError_t launch_jacobian_dense(const KParams& kp, int grid, hipStream_t st) {
@@ -1419,6 +1737,9 @@ static hipError_t set_lds_t(int max_lds) {
   set(reinterpret_cast<const void*>(&k_newton<T, true, 1>));
   set(reinterpret_cast<const void*>(&k_newton<T, true, 2>));
   set(reinterpret_cast<const void*>(&k_newton<T, true, 4>));
+  set(reinterpret_cast<const void*>(&k_adjoint_res<T, 1>));
+  set(reinterpret_cast<const void*>(&k_adjoint_res<T, 2>));
+  set(reinterpret_cast<const void*>(&k_adjoint_res<T, 4>));
   return e;
 }
 

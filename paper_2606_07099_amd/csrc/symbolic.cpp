@@ -104,36 +104,51 @@ int build_level_chunks(const Symbolic& S, int32_t budget_ints, LevelChunks& out,
   }
   // ---- solves: rows of a level with their column lists
   auto solves = [&](const std::vector<int32_t>& lptr, const std::vector<int32_t>& lrows, int32_t nlev,
-                    bool lower, std::vector<int32_t>& ptr, std::vector<int32_t>& blob) -> int {
+                    bool lower, bool pairs, std::vector<int32_t>& ptr, std::vector<int32_t>& blob) -> int {
+    const int32_t w = pairs ? 2 : 1;
     Builder B{&ptr, &blob};
     for (int32_t h = 0; h < nlev; ++h) {
       for (int32_t ri = lptr[h]; ri < lptr[h + 1]; ++ri) {
         const int32_t a = lrows[ri];
         const int32_t p0 = lower ? S.rp[a] : S.diag[a] + 1;
         const int32_t p1 = lower ? S.diag[a] : S.rp[a + 1];
-        const int32_t need = 4 + 4 * (B.n1 + 2) + (int32_t)B.tail.size() + (p1 - p0) + 3;
+        const int32_t need = 4 + 4 * (B.n1 + 2) + (int32_t)B.tail.size() + w * (p1 - p0) + 3;
         if (need > budget_ints && B.n1 > 0) {
-          const int32_t hdr[4] = {B.n1, (int32_t)B.tail.size(), 0, 0};
-          B.emit(hdr, (int32_t)B.tail.size(), -1);
+          const int32_t hdr[4] = {B.n1, (int32_t)B.tail.size() / w, 0, 0};
+          B.emit(hdr, (int32_t)B.tail.size() / w, -1);
         }
-        if (4 + 8 + (p1 - p0) + 3 > budget_ints) {
+        if (4 + 8 + w * (p1 - p0) + 3 > budget_ints) {
           err = "template: a solve row exceeds the metadata chunk budget";
           return -1;
         }
-        B.rec.insert(B.rec.end(), {a, p0, 0, (int32_t)B.tail.size()});
-        for (int32_t p = p0; p < p1; ++p) B.tail.push_back(S.ci[p]);
+        B.rec.insert(B.rec.end(), {a, p0, 0, (int32_t)B.tail.size() / w});
+        for (int32_t p = p0; p < p1; ++p) {
+          B.tail.push_back(S.ci[p]);
+          if (pairs) B.tail.push_back(S.mirror[p]);
+        }
         B.n1++;
       }
-      const int32_t hdr[4] = {B.n1, (int32_t)B.tail.size(), 0, 0};
-      B.emit(hdr, (int32_t)B.tail.size(), -1);
+      const int32_t hdr[4] = {B.n1, (int32_t)B.tail.size() / w, 0, 0};
+      B.emit(hdr, (int32_t)B.tail.size() / w, -1);
     }
     ptr.push_back((int32_t)blob.size());
     out.max_ints = std::max(out.max_ints, B.max_ints);
     return 0;
   };
-  if (solves(S.lev_l_ptr, S.lev_l_rows, S.n_fs_levels, true, out.fs_ptr, out.fs_blob)) return -1;
-  if (solves(S.lev_um_ptr, S.lev_um_rows, (int32_t)S.lev_um_ptr.size() - 1, false, out.bs_ptr, out.bs_blob))
-    return -1;
+  const int32_t nbs = (int32_t)S.lev_um_ptr.size() - 1;
+  if (solves(S.lev_l_ptr, S.lev_l_rows, S.n_fs_levels, true, false, out.fs_ptr, out.fs_blob)) return -1;
+  if (solves(S.lev_um_ptr, S.lev_um_rows, nbs, false, false, out.bs_ptr, out.bs_blob)) return -1;
+  if (solves(S.lev_l_ptr, S.lev_l_rows, S.n_fs_levels, true, true, out.ut_ptr, out.ut_blob)) return -1;
+  if (solves(S.lev_um_ptr, S.lev_um_rows, nbs, false, true, out.lt_ptr, out.lt_blob)) return -1;
+  out.tt_ptr.assign(S.tail_t + 1, 0);
+  for (int32_t l = 0; l < S.tail_t; ++l) {
+    const int32_t a = tb + l;
+    for (int32_t p = S.rp[a]; p < S.tail_split[l]; ++p) {
+      out.tt_pairs.push_back(S.ci[p]);
+      out.tt_pairs.push_back(S.mirror[p]);
+    }
+    out.tt_ptr[l + 1] = (int32_t)out.tt_pairs.size() / 2;
+  }
   (void)nb;
   (void)tb;
   return 0;

@@ -111,10 +111,19 @@ struct Symbolic {
 //           0, first column}, ncol column indices (forward: the L part of
 //           each row, backward: the U part right of the diagonal).
 // The trailing record of each list only carries the end index.
+//  transposed solves (adjoint): as the solves, with a pair (column,
+//           position of the transposed block) per entry: U^T by the forward
+//           levels over the L part of each row, L^T by the backward levels
+//           over the U part.
 struct LevelChunks {
   std::vector<int32_t> f_ptr, f_blob;     // factor tasks
   std::vector<int32_t> fs_ptr, fs_blob;   // forward solve, rows outside the tail
   std::vector<int32_t> bs_ptr, bs_blob;   // backward solve, rows outside the tail
+  std::vector<int32_t> ut_ptr, ut_blob;   // U^T solve, rows outside the tail
+  std::vector<int32_t> lt_ptr, lt_blob;   // L^T solve, rows outside the tail
+  // U^T terms of the tail rows on rows outside the tail: for tail row l the
+  // pairs (column k, position of block (k, tail_base + l)), [tt_ptr[l], tt_ptr[l+1])
+  std::vector<int32_t> tt_ptr, tt_pairs;
   int32_t max_ints = 0;                   // largest chunk, int32 words
 };
 
