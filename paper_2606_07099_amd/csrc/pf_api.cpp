@@ -31,7 +31,8 @@ struct pf_template {
   sable::StateLayout lay{};  // HBM workspace, per scenario
   sable::StateLayout llay{}; // inside an LDS-resident slice, per scenario
   sable::StateLayout alay{}; // inside an LDS-resident adjoint slice, per scenario
-  int adj_slice = 0;         // > 0: LDS-resident adjoint slices of this width
+  int adj_slice = 0;         // > 0: LDS-resident adjoint slices of this width, < 0: HBM-resident
+  int adj_nt = 256;
   size_t adj_lds = 0;
   sable::SymOffsets so{};
   sable::Dims dims{};
@@ -379,7 +380,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   if (best_s > 0) {
     for (int sl : {4, 2, 1}) {
       const size_t need = sable::kScratchBytes + (size_t)so.adj_bytes + sl * per_adj;
-      if (need <= max_lds) { t->adj_slice = sl; t->adj_lds = need; break; }
+      if (need <= max_lds) { t->adj_slice = sl; t->adj_nt = sable::kResThreads; t->adj_lds = need; break; }
     }
   }
   if (best_s > 0) {
@@ -396,6 +397,10 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     while (sl < sable::kMaxSlice && batch / (2 * sl) >= n_cu) sl *= 2;
     t->slice = sl;
     t->lds_bytes = sable::kScratchBytes + 4 * (size_t)chunks.max_ints;
+    // the adjoint reads this slice workspace in place
+    t->adj_slice = -sl;
+    t->adj_nt = std::min(512, std::max(256, 64 * sl));
+    t->adj_lds = t->lds_bytes;
     // a full workgroup of 16 wavefronts: measured fastest for every slice
     // width (more lanes per level of the elimination schedule)
     if (nt == 0) nt = 1024;
@@ -495,9 +500,10 @@ int pf_adjoint_batch(pf_template* t, const double* g_vm, const double* g_va, dou
   kp.mode = sable::MODE_SOLVE;
   kp.g_vm = g_vm; kp.g_va = g_va;
   kp.g_pd = g_pd; kp.g_qd = g_qd; kp.g_pg = g_pg; kp.g_vset = g_vset;
-  const int agrid = t->adj_slice ? (t->batch + t->adj_slice - 1) / t->adj_slice : t->batch;
-  hipError_t he = sable::launch_adjoint(kp, t->fp32, t->adj_slice, agrid, t->adj_slice ? sable::kResThreads : t->nt,
-                                        t->adj_lds, static_cast<hipStream_t>(hip_stream));
+  const int aw = t->adj_slice < 0 ? -t->adj_slice : t->adj_slice;
+  const int agrid = aw ? (t->batch + aw - 1) / aw : t->batch;
+  hipError_t he = sable::launch_adjoint(kp, t->fp32, t->adj_slice, agrid, aw ? t->adj_nt : t->nt, t->adj_lds,
+                                        static_cast<hipStream_t>(hip_stream));
   if (he != hipSuccess) return hip_fail(he, "pf_adjoint_batch: launch");
   return PF_OK;
 }
@@ -535,9 +541,9 @@ int pf_eval_batch(pf_template* t, int32_t mode, int32_t count, const double* pd,
       he = sable::launch_newton(kp, t->fp32, t->slice, grid, t->nt, t->lds_bytes, t->lds_res, st);
       if (he == hipSuccess) {
         kp.mode = sable::MODE_EVAL_ADJOINT;
-        he = sable::launch_adjoint(kp, t->fp32, t->adj_slice,
-                                   t->adj_slice ? (count + t->adj_slice - 1) / t->adj_slice : count,
-                                   t->adj_slice ? sable::kResThreads : t->nt, t->adj_lds, st);
+        const int aw = t->adj_slice < 0 ? -t->adj_slice : t->adj_slice;
+        he = sable::launch_adjoint(kp, t->fp32, t->adj_slice, aw ? (count + aw - 1) / aw : count,
+                                   aw ? t->adj_nt : t->nt, t->adj_lds, st);
       }
       break;
     default:

@@ -100,8 +100,9 @@ constexpr int kResMaxSlice = 4;
 // slice = scenarios per workgroup: 1, 2 or 4 when LDS-resident, up to 16 otherwise.
 hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds,
                          bool lds_res, hipStream_t st);
-// slice > 0: LDS-resident adjoint slices of that width (256 threads), else
-// one scenario per workgroup with HBM-resident factors
+// slice > 0: LDS-resident adjoint slices of that width (256 threads);
+// slice < 0: HBM-resident slices of width -slice reading the forward solve's
+// slice workspace (at most 512 threads); 0: one scenario per workgroup
 hipError_t launch_adjoint(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds, hipStream_t st);
 hipError_t launch_jacobian_dense(const KParams& kp, int grid, hipStream_t st);
 hipError_t set_lds_limits(size_t max_lds);

@@ -1302,10 +1302,12 @@ __global__ void __launch_bounds__(1024) k_adjoint(KParams kp) {
 }
 
 // ----------------------------------------------------------------------------
-// LDS-resident adjoint slices (small grids): S scenarios per workgroup, the
-// kept state and factors copied into LDS, level metadata chunks in place in
-// the LDS image, the transposed dense tail in registers.  Same arithmetic as
-// k_adjoint.
+// adjoint slices: S scenarios per workgroup.  LDS-resident (small grids):
+// the kept state and factors copied into LDS, level metadata chunks in place
+// in the LDS image.  HBM-resident: the slice workspace of the forward solve
+// (state and factors interleaved by scenario) read in place, metadata chunks
+// staged in LDS.  The transposed dense tail in registers, one wavefront per
+// scenario.  Same arithmetic as k_adjoint.
 
 // metadata of the transposed solves
 struct AdjSym {
@@ -1320,13 +1322,14 @@ __device__ __forceinline__ AdjSym bind_adj(const unsigned char* b, const SymOffs
 // U^T w = g by forward levels (UT) or L^T l = w by backward levels, rows
 // outside the tail, in place in y; entries are (column, position of the
 // transposed block) pairs
-template <typename T, int S, bool UT>
-__device__ __forceinline__ void phase_tsolve(const AdjSym& a, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
+template <typename T, int S, bool RES, bool UT>
+__device__ __forceinline__ void phase_tsolve(const AdjSym& a, const Dims& D, St<T>& c, int tid, int nt, int gmin,
+                                             unsigned char* lds) {
   const int nch = UT ? D.nch_ut : D.nch_lt;
   const int* ptr = UT ? a.ut_ptr : a.lt_ptr;
   const int* blob = UT ? a.ut_blob : a.lt_blob;
   for (int ch = 0; ch < nch; ++ch) {
-    const int* h = blob + ptr[ch];
+    const int* h = stage_chunk<!RES>(ptr, blob, ch, lds, tid, nt);
     const int nrow = h[0];
     const int4* rw = reinterpret_cast<const int4*>(h + 4);
     const int* cols = reinterpret_cast<const int*>(rw + nrow + 1);
@@ -1467,29 +1470,37 @@ __device__ __forceinline__ void phase_adj_residual_s(const Sym& m, const Dims& D
   __syncthreads();
 }
 
-template <typename T, int S>
-__global__ void __launch_bounds__(kResThreads) k_adjoint_res(KParams kp) {
+template <typename T, bool RES, int S>
+__global__ void __launch_bounds__(RES ? kResThreads : 512) k_adjoint_slice(KParams kp) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int slice = blockIdx.x;
   const Dims& D = kp.dims;
   int* s_ok = reinterpret_cast<int*>(smem + kPivOff);
-  {   // the shared image prefix (Newton arrays, then the adjoint's), 16 bytes per lane
+  unsigned char* stg = smem + kScratchBytes;   // HBM: staged metadata chunks
+  const unsigned char* img = RES ? smem + kScratchBytes : kp.sym;
+  if (RES) {   // the shared image prefix (Newton arrays, then the adjoint's), 16 bytes per lane
     int4* dst = reinterpret_cast<int4*>(smem + kScratchBytes);
     const int4* src = reinterpret_cast<const int4*>(kp.sym);
     for (int q = tid; q < (kp.so.adj_bytes >> 4); q += nt) dst[q] = src[q];
   }
-  const unsigned char* img = smem + kScratchBytes;
   Sym m = bind_sym(img, kp.sym, kp.so);
   m.y_tr = reinterpret_cast<const int*>(img + kp.so.y_tr);
   const AdjSym as = bind_adj(img, kp.so);
-  double* dbase = reinterpret_cast<double*>(smem + kScratchBytes + kp.so.adj_bytes);
-  St<T> c = bind_state<T, S>(dbase, reinterpret_cast<T*>(dbase + (size_t)kp.alay.sd * S), kp.alay);
+  St<T> c;
+  if (RES) {
+    double* dbase = reinterpret_cast<double*>(smem + kScratchBytes + kp.so.adj_bytes);
+    c = bind_state<T, S>(dbase, reinterpret_cast<T*>(dbase + (size_t)kp.alay.sd * S), kp.alay);
+  } else {
+    c = bind_state<T, S>(kp.wsl_d + (size_t)slice * S * kp.lay.sd,
+                         reinterpret_cast<T*>(kp.wsl_t) + (size_t)slice * S * kp.lay.st, kp.lay);
+  }
   const int n = D.n_bus, nb = D.nb;
   const bool eval = kp.mode == MODE_EVAL_ADJOINT;
-  const int wv = tid >> 6, ln = tid & 63;
+  const int wv = tid >> 6, ln = tid & 63, nw = nt >> 6;
 
   // kept state and factors of the slice's scenarios (padding scenarios: flat, identity)
+  if (RES) {
   for (int idx = tid; idx < n * S; idx += nt) {
     const int i = idx / S, s = idx % S;
     const int b = slice * S + s;
@@ -1515,6 +1526,7 @@ __global__ void __launch_bounds__(kResThreads) k_adjoint_res(KParams kp) {
     const int b = slice * S + s;
     c.dinv[q] = b < kp.count ? reinterpret_cast<const T*>(kp.ws_t)[(size_t)b * kp.lay.st + kp.lay.o_dinv + 4 * p + comp]
                              : ((comp == 0 || comp == 3) ? T(1) : T(0));
+  }
   }
   if (tid < S) {
     const int b = slice * S + tid;
@@ -1554,10 +1566,10 @@ __global__ void __launch_bounds__(kResThreads) k_adjoint_res(KParams kp) {
   __syncthreads();
   const int gmin = S > 4 ? S : 4;
   auto solve = [&]() {
-    phase_tsolve<T, S, true>(as, D, c, tid, nt, gmin);
-    if (wv < S) rt_tsolve<T, S>(m, as, D, c, wv, ln);
+    phase_tsolve<T, S, RES, true>(as, D, c, tid, nt, gmin, stg);
+    for (int s = wv; s < S; s += nw) rt_tsolve<T, S>(m, as, D, c, s, ln);
     __syncthreads();
-    phase_tsolve<T, S, false>(as, D, c, tid, nt, gmin);
+    phase_tsolve<T, S, RES, false>(as, D, c, tid, nt, gmin, stg);
   };
   solve();
   for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
@@ -1697,16 +1709,34 @@ hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int 
 }
 
 template <typename T>
+static hipError_t launch_adjoint_hbm_t(const KParams& kp, int slice, int grid, int nt, size_t lds, hipStream_t st);
+
+template <typename T>
 static hipError_t launch_adjoint_t(const KParams& kp, int slice, int grid, int nt, size_t lds, hipStream_t st) {
   if (slice == 0) {
     hipLaunchKernelGGL((k_adjoint<T>), dim3(grid), dim3(nt), 0, st, kp);
     return hipGetLastError();
   }
+  if (slice < 0) return launch_adjoint_hbm_t<T>(kp, -slice, grid, nt, lds, st);
   if (nt != kResThreads) return hipErrorInvalidValue;
   switch (slice) {
-    case 1: hipLaunchKernelGGL((k_adjoint_res<T, 1>), dim3(grid), dim3(nt), lds, st, kp); break;
-    case 2: hipLaunchKernelGGL((k_adjoint_res<T, 2>), dim3(grid), dim3(nt), lds, st, kp); break;
-    case 4: hipLaunchKernelGGL((k_adjoint_res<T, 4>), dim3(grid), dim3(nt), lds, st, kp); break;
+    case 1: hipLaunchKernelGGL((k_adjoint_slice<T, true, 1>), dim3(grid), dim3(nt), lds, st, kp); break;
+    case 2: hipLaunchKernelGGL((k_adjoint_slice<T, true, 2>), dim3(grid), dim3(nt), lds, st, kp); break;
+    case 4: hipLaunchKernelGGL((k_adjoint_slice<T, true, 4>), dim3(grid), dim3(nt), lds, st, kp); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_adjoint_hbm_t(const KParams& kp, int slice, int grid, int nt, size_t lds, hipStream_t st) {
+  if (nt > 512) return hipErrorInvalidValue;
+  switch (slice) {
+    case 1: hipLaunchKernelGGL((k_adjoint_slice<T, false, 1>), dim3(grid), dim3(nt), lds, st, kp); break;
+    case 2: hipLaunchKernelGGL((k_adjoint_slice<T, false, 2>), dim3(grid), dim3(nt), lds, st, kp); break;
+    case 4: hipLaunchKernelGGL((k_adjoint_slice<T, false, 4>), dim3(grid), dim3(nt), lds, st, kp); break;
+    case 8: hipLaunchKernelGGL((k_adjoint_slice<T, false, 8>), dim3(grid), dim3(nt), lds, st, kp); break;
+    case 16: hipLaunchKernelGGL((k_adjoint_slice<T, false, 16>), dim3(grid), dim3(nt), lds, st, kp); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1737,9 +1767,9 @@ static hipError_t set_lds_t(int max_lds) {
   set(reinterpret_cast<const void*>(&k_newton<T, true, 1>));
   set(reinterpret_cast<const void*>(&k_newton<T, true, 2>));
   set(reinterpret_cast<const void*>(&k_newton<T, true, 4>));
-  set(reinterpret_cast<const void*>(&k_adjoint_res<T, 1>));
-  set(reinterpret_cast<const void*>(&k_adjoint_res<T, 2>));
-  set(reinterpret_cast<const void*>(&k_adjoint_res<T, 4>));
+  set(reinterpret_cast<const void*>(&k_adjoint_slice<T, true, 1>));
+  set(reinterpret_cast<const void*>(&k_adjoint_slice<T, true, 2>));
+  set(reinterpret_cast<const void*>(&k_adjoint_slice<T, true, 4>));
   return e;
 }
 
