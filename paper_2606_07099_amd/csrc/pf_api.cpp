@@ -309,7 +309,18 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   // level metadata in chunks of whole rows: read in place from the LDS image
   // by LDS-resident slices, staged chunk by chunk in LDS by HBM-resident ones
   sable::LevelChunks chunks;
-  rc = sable::build_level_chunks(S, kChunkInts, chunks, err);
+  // HBM-resident slices stage metadata chunks and may keep the tail in LDS:
+  // shrink the chunk budget (not below 2048 words) so that both fit
+  const int n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  int hbm_slice = 1;
+  while (hbm_slice < sable::kMaxSlice && batch / (2 * hbm_slice) >= n_cu) hbm_slice *= 2;
+  const size_t hbm_tail_bytes = (size_t)hbm_slice * tsz * (4 * S.tail_cblk.size() + 6 * (size_t)S.tail_t);
+  int32_t budget = kChunkInts;
+  if (S.tail_t > 0 && sable::kScratchBytes + hbm_tail_bytes + 4 * 2048 <= max_lds) {
+    const size_t room = (max_lds - sable::kScratchBytes - hbm_tail_bytes) / 4;
+    budget = (int32_t)std::min<size_t>(kChunkInts, room / 4 * 4);
+  }
+  rc = sable::build_level_chunks(S, budget, chunks, err);
   if (rc != 0) { delete t; return fail(PF_EINVAL, err); }
   so.bus_type = (int)pk.add(S.bus_type); so.bus_blk = (int)pk.add(S.bus_blk);
   so.y_rp = (int)pk.add(S.y_rp); so.y_ci = (int)pk.add(S.y_ci);
@@ -327,6 +338,8 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   so.tt_ptr = (int)pk.add(chunks.tt_ptr); so.tt_pairs = (int)pk.add(chunks.tt_pairs);
   so.y_tr = (int)pk.add(S.y_tr);
   so.adj_bytes = (int)pk.align();
+  so.tail_cblk = (int)pk.add(S.tail_cblk); so.tail_lbase = (int)pk.add(S.tail_lbase);
+  so.tail_cpos = (int)pk.add(S.tail_cpos);
   so.task_ptr = (int)pk.add(S.task_ptr);
   so.task4 = (int)pk.add(S.task4); so.step4 = (int)pk.add(S.step4);
   so.step_ts = (int)pk.add(S.step_ts); so.upd_tgt = (int)pk.add(S.upd_tgt);
@@ -348,6 +361,8 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   dm.nch_fs = (int)chunks.fs_ptr.size() - 1;
   dm.nch_bs = (int)chunks.bs_ptr.size() - 1;
   dm.chunk_ints = chunks.max_ints;
+  dm.tail_nblk = (int)S.tail_cblk.size();
+  dm.tail_lds = 0;
   dm.nch_ut = (int)chunks.ut_ptr.size() - 1;
   dm.nch_lt = (int)chunks.lt_ptr.size() - 1;
 
@@ -392,11 +407,14 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     // HBM-resident: S scenarios interleaved per slice, S as large as keeps
     // at least one slice per compute unit
     t->lds_res = false;
-    const int n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    int sl = 1;
-    while (sl < sable::kMaxSlice && batch / (2 * sl) >= n_cu) sl *= 2;
+    const int sl = hbm_slice;
     t->slice = sl;
     t->lds_bytes = sable::kScratchBytes + 4 * (size_t)chunks.max_ints;
+    // the tail (its tail-column blocks and pivot inverses) in LDS when it fits
+    if (S.tail_t > 0 && t->lds_bytes + hbm_tail_bytes <= max_lds) {
+      t->dims.tail_lds = 1;
+      t->lds_bytes += hbm_tail_bytes;
+    }
     // the adjoint reads this slice workspace in place
     t->adj_slice = -sl;
     t->adj_nt = std::min(512, std::max(256, 64 * sl));

@@ -44,6 +44,7 @@ struct SymOffsets {
   // [newton_bytes, adj_bytes): what the LDS-resident adjoint reads besides
   int ut_ptr, ut_blob, lt_ptr, lt_blob, tt_ptr, tt_pairs, y_tr;
   int adj_bytes;
+  int tail_cblk, tail_lbase, tail_cpos;   // compact tail numbering (LDS copy of the tail)
   int task_ptr, task4, step4, step_ts, upd_tgt;
   int lev_l_ptr, lev_l_rows, lev_um_ptr, lev_um_rows, tk_ptr, tstep4;
   int lev_u_ptr, lev_u_rows;
@@ -59,6 +60,8 @@ struct Dims {
   int nch_f, nch_fs, nch_bs;      // metadata chunks of the factor, forward and backward levels
   int nch_ut, nch_lt;             // metadata chunks of the transposed solves
   int chunk_ints;                 // largest chunk (int32 words), staged after the LDS scratch
+  int tail_nblk;                  // tail blocks in tail columns
+  int tail_lds;                   // HBM slices: 1 if the tail is factored and solved in an LDS copy
 };
 
 // Offsets of the per-scenario arrays, in elements.  FP64 arrays:

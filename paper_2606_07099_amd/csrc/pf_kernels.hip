@@ -63,6 +63,7 @@ struct Sym {
   const unsigned* tail_mask;
   const int *blk_bus, *lu_src, *mirror, *y_tr, *ord_p, *ord_q;
   const int *f_ptr, *f_blob, *fs_ptr, *fs_blob, *bs_ptr, *bs_blob;
+  const int *tail_cblk, *tail_lbase, *tail_cpos;
 };
 
 __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned char* g,
@@ -107,6 +108,9 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
   m.y_tr = I(g, o.y_tr);   // LDS-resident adjoint slices rebind it to their LDS copy
   m.ord_p = I(g, o.ord_p);
   m.ord_q = I(g, o.ord_q);
+  m.tail_cblk = I(g, o.tail_cblk);
+  m.tail_lbase = I(g, o.tail_lbase);
+  m.tail_cpos = I(g, o.tail_cpos);
   return m;
 }
 
@@ -669,6 +673,165 @@ __device__ __forceinline__ void phase_tail_bsolve(const Sym& m, const Dims& D, S
 }
 
 // ----------------------------------------------------------------------------
+// the tail of HBM-resident slices in an LDS copy: its tail-column blocks in a
+// compact numbering (tl, interleaved by scenario) and its pivot inverses (td)
+// are copied in after the barrier-synchronised part of the factorisation,
+// factored and solved there by the same per-pivot elimination, one
+// wavefront per scenario, and written back only when the factors are kept
+
+template <typename T, int S>
+__device__ __forceinline__ void ltail_copy(const Sym& m, const Dims& D, St<T>& c, T* tl, int tid, int nt,
+                                           bool out) {
+  const int nq = D.tail_nblk * S * 4;
+  for (int q = tid; q < nq; q += nt) {
+    const int comp = q & 3, blk = q >> 2, cb = blk / S, s = blk % S;
+    T* g = c.lu + sB<S>(m.tail_cblk[cb], s) + comp;
+    if (out) *g = tl[q];
+    else tl[q] = *g;
+  }
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void ltail_store_dinv(const Dims& D, St<T>& c, const T* td, int tid, int nt) {
+  for (int q = tid; q < D.tail_t * S * 4; q += nt) c.dinv[sB<S>(D.tail_base, 0) + q] = td[q];
+}
+
+// ty: LDS copy of the tail rows' right-hand sides for the fused forward
+// solve (t x 2 per scenario), written back at the end
+template <typename T, int S>
+__device__ __forceinline__ void ltail_factor(const Sym& m, const Dims& D, St<T>& c, T* tl, T* td, T* ty, int tid,
+                                             int nt, bool fwd, int* piv) {
+  const int t = D.tail_t, tb = D.tail_base;
+  const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
+  for (int s = w; s < S; s += nw) {
+    if (fwd && l < t) {
+      ty[sP<S>(l, s)] = c.y[sP<S>(tb + l, s)];
+      ty[sP<S>(l, s) + 1] = c.y[sP<S>(tb + l, s) + 1];
+    }
+    for (int k = 0; k < t; ++k) {
+      const int ak = tb + k;
+      const int lb = m.tail_lbase[k] - m.rp[ak];   // compact index = position + lb on row ak
+      const int dk = m.diag[ak] + lb;
+      Blk<T> Di = {T(0), T(0), T(0), T(0)};
+      if (l == 0) {
+        const Blk<T> Dk = ld_blk(tl + sB<S>(dk, s));
+        const T det = Dk.a * Dk.d - Dk.b * Dk.c;
+        const T inv = recip(det);
+        Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
+        // pivots of the block: a, then the Schur complement d - c b / a
+        const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
+        const bool zero = !(fabs(Dk.a) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
+                          !(fabs(det) > eps * fabs(Dk.a) * (fabs(Dk.c) + fabs(Dk.d))) ||
+                          !isfinite(inv);
+        if (zero) piv[s] = 1;
+        st_blk(td + sB<S>(k, s), Di);
+      }
+      Di = {lane_bcast(Di.a, 0), lane_bcast(Di.b, 0), lane_bcast(Di.c, 0), lane_bcast(Di.d, 0)};
+      const int t0 = m.tk_ptr[k], t1 = m.tk_ptr[k + 1];
+      if (t1 > t0) {
+        T yk0 = T(0), yk1 = T(0);
+        if (fwd) { yk0 = ty[sP<S>(k, s)]; yk1 = ty[sP<S>(k, s) + 1]; }
+        const int ks = m.diag[ak] + 1 + lb, n = m.rp[ak + 1] - m.diag[ak] - 1;
+        int E = 1;
+        while (E < n && E < 64) E <<= 1;
+        const int lg = __builtin_ctz(E), per = 64 >> lg;
+        const int e = l & (E - 1);
+        for (int st = t0 + (l >> lg); st - (l >> lg) < t1; st += per) {
+          if (st >= t1) continue;
+          const int4 r = m.tstep4[st];   // row i, q, first target, -
+          const int wb = m.tail_lbase[r.x - tb];   // compact index of row-relative offset 0
+          const Blk<T> L = mul(ld_blk(tl + sB<S>(wb + r.y, s)), Di);
+          for (int j = e; j < n; j += E) {
+            const Blk<T> U = ld_blk(tl + sB<S>(ks + j, s));
+            T* a = tl + sB<S>(wb + m.upd_tgt[r.z + j], s);
+            Blk<T> x = ld_blk(a);
+            const Blk<T> LU = mul(L, U);
+            x.a -= LU.a; x.b -= LU.b; x.c -= LU.c; x.d -= LU.d;
+            st_blk(a, x);
+          }
+          if (e == 0) {
+            st_blk(tl + sB<S>(wb + r.y, s), L);
+            if (fwd) {
+              ty[sP<S>(r.x - tb, s)] -= L.a * yk0 + L.b * yk1;
+              ty[sP<S>(r.x - tb, s) + 1] -= L.c * yk0 + L.d * yk1;
+            }
+          }
+        }
+      }
+      // the next pivot reads what this one updated: LDS operations of a
+      // wavefront complete in order, so only the compiler must keep it
+      asm volatile("" ::: "memory");
+    }
+    if (fwd && l < t) {
+      c.y[sP<S>(tb + l, s)] = ty[sP<S>(l, s)];
+      c.y[sP<S>(tb + l, s) + 1] = ty[sP<S>(l, s) + 1];
+    }
+  }
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void ltail_fsolve(const Sym& m, const Dims& D, St<T>& c, const T* tl, int tid, int nt) {
+  const int t = D.tail_t, tb = D.tail_base;
+  const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
+  for (int s = w; s < S; s += nw) {
+    T y0 = T(0), y1 = T(0);
+    if (l < t) {
+      const int a = tb + l;
+      y0 = c.y[sP<S>(a, s)];
+      y1 = c.y[sP<S>(a, s) + 1];
+      for (int p = m.rp[a]; p < m.tail_split[l]; ++p) {
+        const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
+        const int k = m.ci[p];
+        const T z0 = c.y[sP<S>(k, s)], z1 = c.y[sP<S>(k, s) + 1];
+        y0 -= L.a * z0 + L.b * z1;
+        y1 -= L.c * z0 + L.d * z1;
+      }
+    }
+    for (int j = 0; j < t; ++j) {
+      const T yj0 = lane_bcast(y0, j), yj1 = lane_bcast(y1, j);
+      if (l > j && l < t) {
+        const int p = m.tail_cpos[l * t + j];
+        if (p >= 0) {
+          const Blk<T> L = ld_blk(tl + sB<S>(p, s));
+          y0 -= L.a * yj0 + L.b * yj1;
+          y1 -= L.c * yj0 + L.d * yj1;
+        }
+      }
+    }
+    if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+  }
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void ltail_bsolve(const Sym& m, const Dims& D, St<T>& c, const T* tl, const T* td,
+                                             int tid, int nt) {
+  const int t = D.tail_t, tb = D.tail_base;
+  const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
+  for (int s = w; s < S; s += nw) {
+    T y0 = T(0), y1 = T(0);
+    if (l < t) { y0 = c.y[sP<S>(tb + l, s)]; y1 = c.y[sP<S>(tb + l, s) + 1]; }
+    for (int j = t - 1; j >= 0; --j) {
+      if (l == j) {
+        const Blk<T> Di = ld_blk(td + sB<S>(j, s));
+        const T x0 = Di.a * y0 + Di.b * y1, x1 = Di.c * y0 + Di.d * y1;
+        y0 = x0;
+        y1 = x1;
+      }
+      const T xj0 = lane_bcast(y0, j), xj1 = lane_bcast(y1, j);
+      if (l < j) {
+        const int p = m.tail_cpos[l * t + j];
+        if (p >= 0) {
+          const Blk<T> U = ld_blk(tl + sB<S>(p, s));
+          y0 -= U.a * xj0 + U.b * xj1;
+          y1 -= U.c * xj0 + U.d * xj1;
+        }
+      }
+    }
+    if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+  }
+}
+
+// ----------------------------------------------------------------------------
 // register-resident dense tail (LDS-resident slices): wavefront w handles the
 // tail of scenario w.  Lanes 2l and 2l + 1 hold the two scalar rows of tail
 // block row l (components a b, resp. c d, of every 2x2 block), as register
@@ -1044,6 +1207,10 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
   const int gmin = kp.gmin > S ? kp.gmin : S;
   const int wv = tid >> 6, ln = tid & 63;   // LDS-resident tails: wavefront wv <-> scenario wv
   unsigned char* stg = smem + kScratchBytes; // HBM-resident slices: staged level metadata
+  T* tl = reinterpret_cast<T*>(smem + kScratchBytes + 4 * (size_t)kp.dims.chunk_ints);   // HBM: LDS tail
+  T* td = tl + (size_t)kp.dims.tail_nblk * S * 4;
+  T* ty = td + (size_t)kp.dims.tail_t * S * 4;
+  const bool ltail = !RES && kp.dims.tail_lds;
   TailRow<T> R;                             // this wavefront's factored tail rows
   while (true) {
     phase_mismatch<T, S>(m, D, c, tid, nt, scr);
@@ -1067,6 +1234,10 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
     phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, true, piv, stg);
     if constexpr (RES) {
       if (wv < S) rt_factor<T, S>(m, D, c, wv, ln, true, piv, R);
+    } else if (ltail) {
+      ltail_copy<T, S>(m, D, c, tl, tid, nt, false);
+      __syncthreads();
+      ltail_factor<T, S>(m, D, c, tl, td, ty, tid, nt, true, piv);
     } else {
       phase_tail_factor<T, S, RES>(m, D, c, tid, nt, true, piv);
     }
@@ -1079,6 +1250,8 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
     if (!act) break;
     if constexpr (RES) {
       if (wv < S) rt_bsolve<T, S>(m, D, c, wv, ln, R);
+    } else if (ltail) {
+      ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt);
     } else {
       phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
     }
@@ -1107,6 +1280,10 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
             rt_fsolve<T, S>(m, D, c, wv, ln, R);
             rt_bsolve<T, S>(m, D, c, wv, ln, R);
           }
+        } else if (ltail) {
+          ltail_fsolve<T, S>(m, D, c, tl, tid, nt);
+          __syncthreads();
+          ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt);
         } else {
           phase_tail_fsolve<T, S, RES>(m, D, c, tid, nt);
           __syncthreads();
@@ -1179,6 +1356,13 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
         rt_factor<T, S>(m, D, c, wv, ln, false, piv, R);
         rt_store<T, S>(m, D, c, wv, ln, R);
       }
+    } else if (ltail) {
+      ltail_copy<T, S>(m, D, c, tl, tid, nt, false);
+      __syncthreads();
+      ltail_factor<T, S>(m, D, c, tl, td, ty, tid, nt, false, piv);
+      __syncthreads();
+      ltail_copy<T, S>(m, D, c, tl, tid, nt, true);
+      ltail_store_dinv<T, S>(D, c, td, tid, nt);
     } else {
       phase_tail_factor<T, S, RES>(m, D, c, tid, nt, false, piv);
     }

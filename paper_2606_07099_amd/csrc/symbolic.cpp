@@ -426,6 +426,17 @@ int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
         S.tail_pos[(size_t)i * t + (S.ci[p] - S.tail_base)] = p;
       }
     }
+    S.tail_cblk.clear();
+    S.tail_lbase.assign(t, 0);
+    S.tail_cpos.assign((size_t)t * t, -1);
+    for (int32_t i = 0; i < t; ++i) {
+      const int32_t a = S.tail_base + i;
+      S.tail_lbase[i] = (int32_t)S.tail_cblk.size() - (S.tail_split[i] - S.rp[a]);
+      for (int32_t p = S.tail_split[i]; p < S.rp[a + 1]; ++p) {
+        S.tail_cpos[(size_t)i * t + (S.ci[p] - S.tail_base)] = (int32_t)S.tail_cblk.size();
+        S.tail_cblk.push_back(p);
+      }
+    }
     S.tail_mask.assign(t ? t + 2 : 0, 0u);
     if (t > 0 && t <= 32)
       for (int32_t i = 0; i < t; ++i)

@@ -75,6 +75,11 @@ struct Symbolic {
   // tail_mask[t] bit j: column j has a nonzero below the diagonal;
   // tail_mask[t + 1] bit j: column j has a nonzero above the diagonal
   std::vector<uint32_t> tail_mask;
+  // compact numbering of the tail rows' blocks in tail columns (for a copy
+  // of the tail in LDS): tail_cblk[c] is the position of compact block c;
+  // compact index of position p of tail row l = tail_lbase[l] + (p - rp[tail_base + l]);
+  // tail_cpos[i*t + j] = compact index of block (tail_base + i, tail_base + j) or -1
+  std::vector<int32_t> tail_cblk, tail_lbase, tail_cpos;
   // elimination steps of the tail pivots, pivot by pivot: tk_ptr[k] .. tk_ptr[k+1]
   // index tstep4 records {row i, q = L position of (i, pivot) - rp[i], first
   // target in upd_tgt, 0}
