@@ -13,6 +13,9 @@ Contents (plain, slow, dense; every function cites the passage it follows):
   Jacobian from the complex-matrix derivative forms, LAPACK ``gesv``.
 * :mod:`oracle.adjoint`   -- implicit-differentiation gradients by a dense
   transposed solve, the training loss, and central finite differences.
+* :mod:`oracle.completion` -- Step-2 explicit recovery of the generation
+  outputs and the gradients of the whole two-step completion (vbar2 through
+  a dense J2, then the Step-1 transposed solve).
 
 Every function is pinned by ``tests/test_oracle_*.py`` against closed forms,
 invariants, finite differences, the paper's printed Jacobian entries
