@@ -5,15 +5,18 @@ Workload (default): synthetic 118-bus meshed grid (tree + 60 extra branches,
 flat start.  One step runs the whole path on the batch, inputs resident in
 HBM: the plain FP64 Newton solve, the mixed-precision solve (FP32 LU
 refactorisation and solves, FP64 mismatch / convergence / update and two
-FP64-residual refinement steps), and one differentiable-layer forward +
-backward (mixed-precision solve keeping the factors + adjoint).  Each part is
-timed with HIP events on the stream the kernels run on.
+FP64-residual refinement steps), one differentiable-layer forward + backward
+(mixed-precision solve keeping the factors + adjoint), the mixed-precision
+solve with adaptive refinement and without refinement, and one layer forward
++ backward through both completion steps (Step-2 recovery of the generation
+block and its backward term).  Each part is timed with HIP events on the
+stream the kernels run on.
 
-``value`` is the mixed-precision solves/s; the FP64 rate and the layer's
-fwd+bwd samples/s are reported beside it.  The roofline entry covers the
-dominant kernel (the mixed-precision Newton kernel): algorithmic bytes per
-launch (see the design doc for the byte model) over its measured average launch
-duration.  ``cpu_baseline`` times the CPU oracle on a bounded sample.
+``value`` is the mixed-precision solves/s; the other rates are reported
+beside it.  The roofline entry covers the dominant kernel (the
+mixed-precision Newton kernel): algorithmic bytes per launch (the model in
+``algorithmic_bytes_per_solve``) over its measured average launch duration.
+``cpu_baseline`` times the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -117,7 +120,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported "
-                                   "(scenarios shard with no exchange; see DESIGN.md)"}))
+                                   "(scenarios are independent and would shard across GPUs with no exchange)"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -141,6 +144,11 @@ def main():
     tplr0 = PFTemplate.from_network(net, B, tol=spec.tol, precision="mixed", keep_factors=False,
                                     refine_steps=0)
     layer = PFLayer(tpllay)
+    # both completion steps (Step 2 recovers the generation block) under a
+    # loss that adds a generation cost and a reactive-reserve penalty
+    layerc = PFLayer(tpllay, recover=True)
+    slack_mask = torch.as_tensor(net.bus_type == 2, device=dev)
+    gen_mask = torch.as_tensor(net.bus_type != 0, device=dev)
     info64, infomp = tpl64.info(), tplmp.info()
 
     out64 = [torch.empty((B, net.n_bus), dtype=torch.float64, device=dev) for _ in range(2)] + \
@@ -158,6 +166,14 @@ def main():
         L = (torch.relu(vm - 1.05) ** 2).sum() + (torch.relu(0.95 - vm) ** 2).sum() + 0.1 * (va ** 2).sum()
         L.backward()
 
+    def layer_completed_step():
+        for v in leaves.values():
+            v.grad = None
+        vm, va, po, qo = layerc(leaves["pd"], leaves["qd"], leaves["pg"], leaves["vset"])
+        L = ((torch.relu(vm - 1.05) ** 2).sum() + (torch.relu(0.95 - vm) ** 2).sum() + 0.1 * (va ** 2).sum()
+             + (po[:, slack_mask] ** 2).sum() + 0.5 * (qo[:, gen_mask] ** 2).sum())
+        L.backward()
+
     if args.copy_reference_mib:
         src = torch.ones(args.copy_reference_mib << 17, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -172,13 +188,14 @@ def main():
         tplad.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=outad)
         tplr0.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=outr0)
         layer_step()
+        layer_completed_step()
     torch.cuda.synchronize()
 
     marks = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        e = [ev() for _ in range(6)]
+        e = [ev() for _ in range(7)]
         e[0].record(stream)
         tpl64.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=out64)
         e[1].record(stream)
@@ -190,6 +207,8 @@ def main():
         e[4].record(stream)
         tplr0.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=outr0)
         e[5].record(stream)
+        layer_completed_step()
+        e[6].record(stream)
         marks.append(e)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -199,6 +218,7 @@ def main():
     tfb = np.array([m[2].elapsed_time(m[3]) for m in marks]) * 1e-3
     tad = np.array([m[3].elapsed_time(m[4]) for m in marks]) * 1e-3
     tr0 = np.array([m[4].elapsed_time(m[5]) for m in marks]) * 1e-3
+    tfc = np.array([m[5].elapsed_time(m[6]) for m in marks]) * 1e-3
     itad, stad, fnad = (x.cpu().numpy() for x in outad[2:])
     itr0, str0, fnr0 = (x.cpu().numpy() for x in outr0[2:])
     it64, st64, fn64 = (x.cpu().numpy() for x in out64[2:])
@@ -229,9 +249,11 @@ def main():
         "layer_fwd_bwd_samples_per_s": B / tfb.mean(),
         "mixed_adaptive_solves_per_s": B / tad.mean(),
         "mixed_unrefined_solves_per_s": B / tr0.mean(),
+        "layer_completed_fwd_bwd_samples_per_s": B / tfc.mean(),
         "ms": {"fp64_solve": 1e3 * t64.mean(), "mixed_solve": 1e3 * tmp.mean(),
                "mixed_adaptive_solve": 1e3 * tad.mean(), "mixed_unrefined_solve": 1e3 * tr0.mean(),
-               "layer_fwd_bwd": 1e3 * tfb.mean(), "template_build": 1e3 * t_build},
+               "layer_fwd_bwd": 1e3 * tfb.mean(), "layer_completed_fwd_bwd": 1e3 * tfc.mean(),
+               "template_build": 1e3 * t_build},
         "iterations": {"fp64": np.bincount(it64).tolist(), "mixed": np.bincount(itmp).tolist(),
                        "mixed_adaptive": np.bincount(itad).tolist(),
                        "mixed_unrefined": np.bincount(itr0).tolist()},

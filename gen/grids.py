@@ -23,12 +23,13 @@ experimental-setup section, kept here as ``scenario_mode="uniform10"``):
 * scenario b scales each PQ load by s ~ LogNormal(0, sigma) (same factor
   for P and Q), and every PV bus dispatches 0.95 * sum_b(p_d) / n_PV;
 * ``load_factor`` < 1 scales the nominal loads (and hence the dispatch)
-  down; it is the feasibility back-off described in the design doc and its
-  per-grid value was chosen by ``oracle/calibrate_load_factor.py``;
+  down; it is a feasibility back-off (the recipe's literal load levels do
+  not converge from the flat start on the larger grids) and its per-grid
+  value was chosen by ``oracle/calibrate_load_factor.py``;
 * ``z_scale`` multiplies the drawn r, x and b: per-unit line parameters grow
   with line length, and on the 9241-bus grid (same unit square) the lines
   are sqrt(9241/118) times shorter than on the 118-bus grid.  Without it no
-  load level converges from the flat start on that grid (see DESIGN.md).
+  load level converges from the flat start on that grid.
 
 Random streams: ``numpy.random.default_rng(SeedSequence([seed, grid_id]))``
 for the network, ``SeedSequence([seed, grid_id, 1])`` for the scenarios, with

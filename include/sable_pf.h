@@ -207,6 +207,50 @@ int pf_adjoint_batch(pf_template* tpl, const double* g_vm, const double* g_va, d
                      double* g_qd, double* g_pg, double* g_vset, void* hip_stream);
 
 /*
+ * Step 2 of the forward completion (eq. F2_completion): the generation block
+ * of the completed PF buffer y (eq. y_and_F_base) at a solution (vm, va).
+ * The equality rows left out of F1 (dP on the slack bus, dQ on PV and slack
+ * buses) are zero at the solution and contain z2 = (p_g on the slack bus,
+ * q_g on PV and slack buses) with unit coefficients, so with
+ * S = P + jQ = V o conj(Y_bus V) evaluated in FP64:
+ *   pg_out = P + pd on the slack bus, pg (x, passed through) on PV buses,
+ *            0 on PQ buses
+ *   qg_out = Q + qd on PV and slack buses, 0 on PQ buses
+ * Device inputs [batch][n_bus]: pd, qd, pg (NULL = zero), vm, va (normally
+ * what pf_solve_batch returned; any state is accepted and every scenario is
+ * evaluated, whatever its solve status).  Device outputs [batch][n_bus]:
+ * pg_out, qg_out (either may be NULL).  Reads only the template's pattern,
+ * not its workspace, so it may run before or after any solve.  Asynchronous
+ * on hip_stream.  Errors: PF_EINVAL (NULL template or input), PF_EHIP.
+ */
+int pf_recover_batch(pf_template* tpl, const double* pd, const double* qd, const double* pg,
+                     const double* vm, const double* va, double* pg_out, double* qg_out,
+                     void* hip_stream);
+
+/*
+ * Adjoint of the full two-step completion (chain-rule equation and the J2
+ * and vbar2 equations of the backward pass, Sec. II-B): as pf_adjoint_batch,
+ * for a loss that also depends on the recovered generation.  Extra device
+ * inputs [batch][n_bus]: g_pg_out = dL/d(pg_out), read on slack and PV
+ * buses, and g_qg_out = dL/d(qg_out), read on PV and slack buses; either may
+ * be NULL (zero).  The kernel forms vbar2 = -J2^T dL/dz2 with
+ * J2 = dF2/d(|V|, theta) (eq. Jstep2_impl) as a transposed product through
+ * Y_bus at the kept state, adds it to g_z1 before the J1^T solve and to the
+ * |V| entries of g_x after it.  Outputs [batch][n_bus] (any may be NULL):
+ *   g_pd   = +lambda_P on non-slack buses; g_pg_out on the slack bus
+ *   g_qd   = +lambda_Q on PQ buses; g_qg_out on PV and slack buses
+ *   g_pg   = g_pg_out - lambda_P on PV buses, 0 elsewhere
+ *   g_vset = g_vm + vbar2 - (J3^T lambda) on PV and slack buses, 0 elsewhere
+ * (the load terms on the generator rows are the unit dependence of z2 on the
+ * load of its own row).  Scenarios whose solve did not converge get zero
+ * gradients.  Errors: PF_EINVAL, PF_ESTATE (no solve yet, or
+ * keep_factors=0), PF_EHIP.
+ */
+int pf_adjoint_completed_batch(pf_template* tpl, const double* g_vm, const double* g_va,
+                               const double* g_pg_out, const double* g_qg_out, double* g_pd,
+                               double* g_qd, double* g_pg, double* g_vset, void* hip_stream);
+
+/*
  * Evaluation entry points at a GIVEN state (vm, va device [batch][n_bus]),
  * for kernel-level checks and interop, in the paper's ordering: rows
  * (dP on B\R ascending bus, then dQ on D ascending bus), unknowns

@@ -4,7 +4,7 @@ Test infrastructure (calls only the oracle and the input generator).  The
 synthetic recipe dispatches 0.95 of the total load on the PV buses and leaves
 the rest plus all losses to the single slack bus; on the larger grids that
 exceeds what the slack's few branches can carry and Newton diverges from the
-flat start.  Reading adopted (listed in the design doc): scale every nominal load
+flat start.  Reading adopted: scale every nominal load
 (and therefore the dispatch) by 0.9**k with the smallest k for which the
 nominal operating point converges from the flat start in at most 10 updates
 with min |V| >= 0.90.  Feasibility is monotone in the load level over the

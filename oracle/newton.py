@@ -8,7 +8,7 @@ eqs. for F1, the linear system and J1).  PV and slack magnitudes are the
 setpoints of the decision block x, the slack angle is 0, and the iteration
 starts flat (|V| = 1 on PQ buses, angles 0; experimental setup, Sec. IV-A).
 
-Readings where the paper is silent (each listed in the design doc):
+Readings where the paper is silent:
 
 * convergence is ||F1||_inf < tol (strict), tested before every update,
   including at the flat start; ``iters`` counts the updates applied;

@@ -19,7 +19,7 @@ PF_EVAL_MISMATCH, PF_EVAL_JACOBIAN, PF_EVAL_STEP, PF_EVAL_ADJOINT = 0, 1, 2, 3
 
 EXPORTED = ("pf_default_options", "pf_last_error", "pf_ybus_from_branches", "pf_template_build",
             "pf_template_info", "pf_template_destroy", "pf_symbolic_analyze", "pf_solve_batch",
-            "pf_adjoint_batch", "pf_eval_batch")
+            "pf_adjoint_batch", "pf_eval_batch", "pf_recover_batch", "pf_adjoint_completed_batch")
 
 
 class PFOptions(ctypes.Structure):
@@ -83,7 +83,7 @@ def lib():
     L.pf_eval_batch.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     for name in ("pf_ybus_from_branches", "pf_template_build", "pf_template_info",
                  "pf_template_destroy", "pf_symbolic_analyze", "pf_solve_batch",
-                 "pf_adjoint_batch", "pf_eval_batch"):
+                 "pf_adjoint_batch", "pf_eval_batch", "pf_recover_batch", "pf_adjoint_completed_batch"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -200,6 +200,29 @@ sable::KParams base_params(const pf_template* t) {
   return kp;
 }
 
+int adjoint_impl(const char* name, pf_template* t, const double* g_vm, const double* g_va,
+                 const double* g_pgo, const double* g_qgo, double* g_pd, double* g_qd, double* g_pg,
+                 double* g_vset, void* hip_stream) {
+  g_err.clear();
+  const std::string nm(name);
+  if (!t) return fail(PF_EINVAL, nm + ": template is NULL");
+  if (!g_vm || !g_va) return fail(PF_EINVAL, nm + ": NULL gradient input");
+  if (!t->have_factors)
+    return fail(PF_ESTATE, nm + ": needs a preceding pf_solve_batch with keep_factors=1");
+  DeviceGuard g(t->device);
+  sable::KParams kp = base_params(t);
+  kp.mode = sable::MODE_SOLVE;
+  kp.g_vm = g_vm; kp.g_va = g_va;
+  kp.g_pgo = g_pgo; kp.g_qgo = g_qgo;
+  kp.g_pd = g_pd; kp.g_qd = g_qd; kp.g_pg = g_pg; kp.g_vset = g_vset;
+  const int aw = t->adj_slice < 0 ? -t->adj_slice : t->adj_slice;
+  const int agrid = aw ? (t->batch + aw - 1) / aw : t->batch;
+  hipError_t he = sable::launch_adjoint(kp, t->fp32, t->adj_slice, agrid, aw ? t->adj_nt : t->nt, t->adj_lds,
+                                        static_cast<hipStream_t>(hip_stream));
+  if (he != hipSuccess) return hip_fail(he, (nm + ": launch").c_str());
+  return PF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -506,23 +529,32 @@ int pf_solve_batch(pf_template* t, const double* pd, const double* qd, const dou
   return PF_OK;
 }
 
+
 int pf_adjoint_batch(pf_template* t, const double* g_vm, const double* g_va, double* g_pd,
                      double* g_qd, double* g_pg, double* g_vset, void* hip_stream) {
+  return adjoint_impl("pf_adjoint_batch", t, g_vm, g_va, nullptr, nullptr, g_pd, g_qd, g_pg, g_vset,
+                      hip_stream);
+}
+
+int pf_adjoint_completed_batch(pf_template* t, const double* g_vm, const double* g_va,
+                               const double* g_pg_out, const double* g_qg_out, double* g_pd,
+                               double* g_qd, double* g_pg, double* g_vset, void* hip_stream) {
+  return adjoint_impl("pf_adjoint_completed_batch", t, g_vm, g_va, g_pg_out, g_qg_out, g_pd, g_qd, g_pg,
+                      g_vset, hip_stream);
+}
+
+int pf_recover_batch(pf_template* t, const double* pd, const double* qd, const double* pg,
+                     const double* vm, const double* va, double* pg_out, double* qg_out,
+                     void* hip_stream) {
   g_err.clear();
-  if (!t) return fail(PF_EINVAL, "pf_adjoint_batch: template is NULL");
-  if (!g_vm || !g_va) return fail(PF_EINVAL, "pf_adjoint_batch: NULL gradient input");
-  if (!t->have_factors)
-    return fail(PF_ESTATE, "pf_adjoint_batch: needs a preceding pf_solve_batch with keep_factors=1");
+  if (!t) return fail(PF_EINVAL, "pf_recover_batch: template is NULL");
+  if (!pd || !qd || !vm || !va) return fail(PF_EINVAL, "pf_recover_batch: NULL input");
   DeviceGuard g(t->device);
   sable::KParams kp = base_params(t);
-  kp.mode = sable::MODE_SOLVE;
-  kp.g_vm = g_vm; kp.g_va = g_va;
-  kp.g_pd = g_pd; kp.g_qd = g_qd; kp.g_pg = g_pg; kp.g_vset = g_vset;
-  const int aw = t->adj_slice < 0 ? -t->adj_slice : t->adj_slice;
-  const int agrid = aw ? (t->batch + aw - 1) / aw : t->batch;
-  hipError_t he = sable::launch_adjoint(kp, t->fp32, t->adj_slice, agrid, aw ? t->adj_nt : t->nt, t->adj_lds,
-                                        static_cast<hipStream_t>(hip_stream));
-  if (he != hipSuccess) return hip_fail(he, "pf_adjoint_batch: launch");
+  kp.pd = pd; kp.qd = qd; kp.pg = pg; kp.vm_in = vm; kp.va_in = va;
+  kp.pg_out = pg_out; kp.qg_out = qg_out;
+  hipError_t he = sable::launch_recover(kp, static_cast<hipStream_t>(hip_stream));
+  if (he != hipSuccess) return hip_fail(he, "pf_recover_batch: launch");
   return PF_OK;
 }
 

@@ -93,6 +93,10 @@ struct KParams {
   const double *pd, *qd, *pg, *vset, *vm_in, *va_in, *rhs, *g_vm, *g_va;
   double *vm_out, *va_out, *fnorm_out, *out, *g_pd, *g_qd, *g_pg, *g_vset;
   int *iters_out, *status_out;
+  // Step 2: recovered generation (outputs) and the loss's gradients on it
+  // (inputs of the completed adjoint); [batch][n_bus], any may be null
+  double *pg_out, *qg_out;
+  const double *g_pgo, *g_qgo;
 };
 
 // LDS-resident slices: one wavefront per scenario for the register-resident
@@ -108,6 +112,8 @@ hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int 
 // slice workspace (at most 512 threads); 0: one scenario per workgroup
 hipError_t launch_adjoint(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds, hipStream_t st);
 hipError_t launch_jacobian_dense(const KParams& kp, int grid, hipStream_t st);
+// Step-2 recovery of the generation block for kp.count scenarios
+hipError_t launch_recover(const KParams& kp, hipStream_t st);
 hipError_t set_lds_limits(size_t max_lds);
 
 }  // namespace sable

@@ -1075,6 +1075,23 @@ __device__ __forceinline__ void phase_residual(const Sym& m, const Dims& D, St<T
   if (norm) block_max<S>(mx, 0, scr, tid, nt);
 }
 
+// loss gradients on the Step-2 outputs as extra weights of the transposed
+// product through Y_bus: dL/dp_g on the slack row (dP), dL/dq_g on PV and
+// slack rows (dQ).  These rows are exactly the ones outside F1, so they never
+// collide with the lambda weights.  [batch][n_bus] arrays, either may be null.
+struct GenW {
+  const double *p = nullptr, *q = nullptr;
+  int b0 = 0, count = 0, n = 0;
+  __device__ __forceinline__ bool on() const { return p || q; }
+  __device__ __forceinline__ void add(int i, int s, int bt, double& nr, double& ni) const {
+    const int b = b0 + s;
+    if (b >= count) return;
+    const size_t o = (size_t)b * n + i;
+    if (p && bt == 2) nr += p[o];
+    if (q && bt != 0) ni += q[o];
+  }
+};
+
 // adjoint residual r = g - J1^T lam in FP64 without forming J1 (transposed
 // directional derivative of S = V conj(Y V)): with nu = lam_P + j lam_Q and
 // c_m = conj(nu_m I_m) + sum_i Y_im nu_i conj(V_i),
@@ -1083,11 +1100,12 @@ __device__ __forceinline__ void phase_residual(const Sym& m, const Dims& D, St<T
 // g == nullptr: only aux is produced.  One scenario (HBM state).
 template <typename T>
 __device__ __forceinline__ void phase_adj_residual(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
-                                   const double* lam, const double* g, bool to_y) {
+                                   const double* lam, double* g, bool to_y, GenW gw = GenW{}) {
   for (int i = tid; i < D.n_bus; i += nt) {   // w_i = nu_i conj(V_i) -> (dvr, dvi)
     const int a = m.bus_blk[i];
     double nr = 0.0, ni = 0.0;
-    if (a >= 0) { nr = lam[2 * a]; ni = m.bus_type[i] == 0 ? lam[2 * a + 1] : 0.0; }
+    if (a >= 0 && lam) { nr = lam[2 * a]; ni = m.bus_type[i] == 0 ? lam[2 * a + 1] : 0.0; }
+    gw.add(i, 0, m.bus_type[i], nr, ni);
     c.dvr[i] = nr * c.e[i] + ni * c.f[i];
     c.dvi[i] = ni * c.e[i] - nr * c.f[i];
   }
@@ -1103,7 +1121,8 @@ __device__ __forceinline__ void phase_adj_residual(const Sym& m, const Dims& D, 
     }
     const int a = m.bus_blk[mb];
     double nr = 0.0, ni = 0.0;
-    if (a >= 0) { nr = lam[2 * a]; ni = m.bus_type[mb] == 0 ? lam[2 * a + 1] : 0.0; }
+    if (a >= 0 && lam) { nr = lam[2 * a]; ni = m.bus_type[mb] == 0 ? lam[2 * a + 1] : 0.0; }
+    gw.add(mb, 0, m.bus_type[mb], nr, ni);
     const double ir = c.ire[mb], ii = c.iim[mb];
     const double cr = (nr * ir - ni * ii) + tr;      // Re c_m
     const double ci = -(nr * ii + ni * ir) + ti;     // Im c_m
@@ -1115,6 +1134,7 @@ __device__ __forceinline__ void phase_adj_residual(const Sym& m, const Dims& D, 
       const double r0 = g[2 * a] - vci;
       const double r1 = m.bus_type[mb] == 0 ? g[2 * a + 1] + vcr / c.vm[mb] : 0.0;
       if (to_y) { c.y[2 * a] = T(r0); c.y[2 * a + 1] = T(r1); }
+      else { g[2 * a] = r0; g[2 * a + 1] = r1; }   // in place: g + (transposed product)
     }
   }
   __syncthreads();
@@ -1393,6 +1413,19 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
   }
 }
 
+// direct Step-2 terms of the gradients: z2 carries the load of its own row
+// with unit weight (p_g,R = P_R + p_d,R, q_g = Q + q_d on PV and slack
+// buses), and the completed p_g on PV buses is x's p_g passed through
+__device__ __forceinline__ void gen_direct(const KParams& kp, size_t o, int bt, double& gpd, double& gqd,
+                                           double& gpg) {
+  if (kp.mode != MODE_SOLVE) return;
+  if (kp.g_pgo) {
+    if (bt == 2) gpd += kp.g_pgo[o];
+    if (bt == 1) gpg += kp.g_pgo[o];
+  }
+  if (kp.g_qgo && bt != 0) gqd += kp.g_qgo[o];
+}
+
 // ----------------------------------------------------------------------------
 // adjoint kernel (one scenario per workgroup, HBM-resident state and factors)
 
@@ -1437,6 +1470,10 @@ __global__ void __launch_bounds__(1024) k_adjoint(KParams kp) {
     c.iim[i] = ii;
   }
   __syncthreads();
+  // Step 2: g_z1 += vbar2 on z1 (vbar2 = -J2^T dL/dz2, a transposed product)
+  GenW gw;
+  if (!eval) { gw.p = kp.g_pgo; gw.q = kp.g_qgo; gw.b0 = b; gw.count = kp.count; gw.n = n; }
+  if (gw.on()) phase_adj_residual<T>(m, D, c, tid, nt, nullptr, c.F, false, gw);
   for (int q = tid; q < 2 * nb; q += nt) c.y[q] = T(c.F[q]);
   __syncthreads();
   phase_ut_solve<T>(m, D, c, tid, nt, 1);
@@ -1465,7 +1502,8 @@ __global__ void __launch_bounds__(1024) k_adjoint(KParams kp) {
     return;
   }
   // J3^T lam via the transposed product at the solution (-(J3^T lam) lands in aux)
-  phase_adj_residual<T>(m, D, c, tid, nt, c.dx, nullptr, false);
+  // (with Step-2 weights the same product also carries vbar2 on |V| of x)
+  phase_adj_residual<T>(m, D, c, tid, nt, c.dx, nullptr, false, gw);
   for (int i = tid; i < n; i += nt) {
     const int a = m.bus_blk[i];
     const int bt = m.bus_type[i];
@@ -1477,6 +1515,7 @@ __global__ void __launch_bounds__(1024) k_adjoint(KParams kp) {
         if (bt == 1) gpg = -c.dx[2 * a];
       }
       if (bt != 0) gvs = kp.g_vm[io + i] + c.aux[i];
+      gen_direct(kp, io + i, bt, gpd, gqd, gpg);
     }
     if (kp.g_pd) kp.g_pd[io + i] = gpd;
     if (kp.g_qd) kp.g_qd[io + i] = gqd;
@@ -1615,12 +1654,14 @@ __device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const D
 // slice: as phase_adj_residual
 template <typename T, int S>
 __device__ __forceinline__ void phase_adj_residual_s(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
-                                                     const double* lam, const double* g, bool to_y) {
+                                                     const double* lam, double* g, bool to_y,
+                                                     GenW gw = GenW{}) {
   for (int idx = tid; idx < D.n_bus * S; idx += nt) {   // w_i = nu_i conj(V_i)
     const int i = idx / S, s = idx % S;
     const int a = m.bus_blk[i];
     double nr = 0.0, ni = 0.0;
-    if (a >= 0) { nr = lam[sP<S>(a, s)]; ni = m.bus_type[i] == 0 ? lam[sP<S>(a, s) + 1] : 0.0; }
+    if (a >= 0 && lam) { nr = lam[sP<S>(a, s)]; ni = m.bus_type[i] == 0 ? lam[sP<S>(a, s) + 1] : 0.0; }
+    gw.add(i, s, m.bus_type[i], nr, ni);
     c.dvr[idx] = nr * c.e[idx] + ni * c.f[idx];
     c.dvi[idx] = ni * c.e[idx] - nr * c.f[idx];
   }
@@ -1637,7 +1678,8 @@ __device__ __forceinline__ void phase_adj_residual_s(const Sym& m, const Dims& D
     }
     const int a = m.bus_blk[mb];
     double nr = 0.0, ni = 0.0;
-    if (a >= 0) { nr = lam[sP<S>(a, s)]; ni = m.bus_type[mb] == 0 ? lam[sP<S>(a, s) + 1] : 0.0; }
+    if (a >= 0 && lam) { nr = lam[sP<S>(a, s)]; ni = m.bus_type[mb] == 0 ? lam[sP<S>(a, s) + 1] : 0.0; }
+    gw.add(mb, s, m.bus_type[mb], nr, ni);
     const double ir = c.ire[idx], ii = c.iim[idx];
     const double cr = (nr * ir - ni * ii) + tr;      // Re c_m
     const double ci = -(nr * ii + ni * ir) + ti;     // Im c_m
@@ -1649,6 +1691,7 @@ __device__ __forceinline__ void phase_adj_residual_s(const Sym& m, const Dims& D
       const double r0 = g[sP<S>(a, s)] - vci;
       const double r1 = m.bus_type[mb] == 0 ? g[sP<S>(a, s) + 1] + vcr / c.vm[idx] : 0.0;
       if (to_y) { c.y[sP<S>(a, s)] = T(r0); c.y[sP<S>(a, s) + 1] = T(r1); }
+      else { g[sP<S>(a, s)] = r0; g[sP<S>(a, s) + 1] = r1; }   // in place
     }
   }
   __syncthreads();
@@ -1746,6 +1789,10 @@ __global__ void __launch_bounds__(RES ? kResThreads : 512) k_adjoint_slice(KPara
     c.F[sP<S>(a, s) + 1] = g1;
   }
   __syncthreads();
+  // Step 2: g_z1 += vbar2 on z1 (vbar2 = -J2^T dL/dz2, a transposed product)
+  GenW gw;
+  if (!eval) { gw.p = kp.g_pgo; gw.q = kp.g_qgo; gw.b0 = slice * S; gw.count = kp.count; gw.n = n; }
+  if (gw.on()) phase_adj_residual_s<T, S>(m, D, c, tid, nt, nullptr, c.F, false, gw);
   for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(c.F[q]);
   __syncthreads();
   const int gmin = S > 4 ? S : 4;
@@ -1779,7 +1826,8 @@ __global__ void __launch_bounds__(RES ? kResThreads : 512) k_adjoint_slice(KPara
     return;
   }
   // J3^T lam via the transposed product at the solution (-(J3^T lam) lands in aux)
-  phase_adj_residual_s<T, S>(m, D, c, tid, nt, c.dx, nullptr, false);
+  // (with Step-2 weights the same product also carries vbar2 on |V| of x)
+  phase_adj_residual_s<T, S>(m, D, c, tid, nt, c.dx, nullptr, false, gw);
   for (int idx = tid; idx < n * S; idx += nt) {
     const int i = idx / S, s = idx % S;
     const int b = slice * S + s;
@@ -1795,12 +1843,51 @@ __global__ void __launch_bounds__(RES ? kResThreads : 512) k_adjoint_slice(KPara
         if (bt == 1) gpg = -c.dx[sP<S>(a, s)];
       }
       if (bt != 0) gvs = kp.g_vm[o] + c.aux[idx];
+      gen_direct(kp, o, bt, gpd, gqd, gpg);
     }
     if (kp.g_pd) kp.g_pd[o] = gpd;
     if (kp.g_qd) kp.g_qd[o] = gqd;
     if (kp.g_pg) kp.g_pg[o] = gpg;
     if (kp.g_vset) kp.g_vset[o] = gvs;
   }
+}
+
+// ----------------------------------------------------------------------------
+// Step 2 of the forward completion: the generation block of y at a given
+// solution.  One thread per (scenario, bus); PQ rows write zeros.  The
+// calculated injection of a PV or slack row is one Y_bus row product in FP64,
+// with the voltages of its neighbours formed from (|V|, theta) on the fly.
+
+__global__ void __launch_bounds__(256) k_recover(KParams kp) {
+  const Sym m = bind_sym(kp.sym, kp.sym, kp.so);
+  const int n = kp.dims.n_bus;
+  const size_t o = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (o >= (size_t)kp.count * n) return;
+  const size_t row = o - o % n;
+  const int i = (int)(o % n);
+  const int bt = m.bus_type[i];
+  double po = 0.0, qo = 0.0;
+  if (bt != 0) {
+    const double* vm = kp.vm_in + row;
+    const double* va = kp.va_in + row;
+    double ir = 0.0, ii = 0.0;
+    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
+      const int j = m.y_ci[q];
+      double sn, cs;
+      sincos(va[j], &sn, &cs);
+      const double ej = vm[j] * cs, fj = vm[j] * sn;
+      ir += m.y_g[q] * ej - m.y_b[q] * fj;
+      ii += m.y_g[q] * fj + m.y_b[q] * ej;
+    }
+    double sn, cs;
+    sincos(va[i], &sn, &cs);
+    const double e = vm[i] * cs, f = vm[i] * sn;
+    const double P = e * ir + f * ii, Q = f * ir - e * ii;   // S = V conj(I)
+    qo = Q + kp.qd[o];
+    po = bt == 2 ? P + kp.pd[o] : (kp.pg ? kp.pg[o] : 0.0);
+  }
+  if (kp.pg_out) kp.pg_out[o] = po;
+  if (kp.qg_out) kp.qg_out[o] = qo;
 }
 
 // ----------------------------------------------------------------------------
@@ -1929,6 +2016,13 @@ static hipError_t launch_adjoint_hbm_t(const KParams& kp, int slice, int grid, i
 hipError_t launch_adjoint(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds, hipStream_t st) {
   return fp32 ? launch_adjoint_t<float>(kp, slice, grid, nt, lds, st)
               : launch_adjoint_t<double>(kp, slice, grid, nt, lds, st);
+}
+
+hipError_t launch_recover(const KParams& kp, hipStream_t st) {
+  const size_t total = (size_t)kp.count * kp.dims.n_bus;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_recover, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, kp);
+  return hipGetLastError();
 }
 
 hipError_t launch_jacobian_dense(const KParams& kp, int grid, hipStream_t st) {

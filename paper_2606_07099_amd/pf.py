@@ -168,6 +168,31 @@ class PFTemplate:
                                      _stream_ptr(stream)))
         return tuple(outs)
 
+    def recover(self, pd, qd, pg, vm, va, *, stream=None):
+        """Step-2 generation block (pg_out, qg_out) at the solution (vm, va)."""
+        import torch
+        pg_out = torch.empty_like(vm)
+        qg_out = torch.empty_like(vm)
+        check(lib().pf_recover_batch(self._h, self._check("pd", pd), self._check("qd", qd),
+                                     self._check("pg", pg) if pg is not None else ctypes.c_void_p(0),
+                                     self._check("vm", vm), self._check("va", va),
+                                     ctypes.c_void_p(pg_out.data_ptr()),
+                                     ctypes.c_void_p(qg_out.data_ptr()), _stream_ptr(stream)))
+        return pg_out, qg_out
+
+    def adjoint_completed(self, g_vm, g_va, g_pg_out=None, g_qg_out=None, *, stream=None):
+        """Gradients (g_pd, g_qd, g_pg, g_vset) of the most recent solve for a
+        loss on (vm, va) and on the recovered generation (pg_out, qg_out)."""
+        import torch
+        outs = [torch.empty_like(g_vm) for _ in range(4)]
+        opt = [self._check(k, v) if v is not None else ctypes.c_void_p(0)
+               for k, v in (("g_pg_out", g_pg_out), ("g_qg_out", g_qg_out))]
+        check(lib().pf_adjoint_completed_batch(self._h, self._check("g_vm", g_vm),
+                                               self._check("g_va", g_va), *opt,
+                                               *[ctypes.c_void_p(o.data_ptr()) for o in outs],
+                                               _stream_ptr(stream)))
+        return tuple(outs)
+
     def evaluate(self, mode, pd, qd, pg, vset, vm, va, rhs=None, count=None, *, stream=None):
         """Kernel-level evaluation at a given state (see ``pf_eval_batch``)."""
         import torch
