@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c1", help="grid name in gen.grids.SPECS")
+    ap.add_argument("--scenarios", default="lognormal", choices=("lognormal", "uniform10"),
+                    help="load scenarios: lognormal scaling of each PQ load, or the paper's "
+                         "independent uniform +-10%% perturbation of P and Q")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-reference-mib", type=int, default=0,
@@ -75,11 +78,11 @@ def algorithmic_bytes_per_solve(n_bus, nnz_lu, iters, w, refine):
 
 
 def _oracle_worker(args):
-    name, batch, idx = args
+    name, batch, idx, mode = args
     from gen.grids import make_case
     from oracle.newton import newton
     from oracle.ybus import ybus_of
-    spec, net, sc = make_case(name, batch=batch)
+    spec, net, sc = make_case(name, batch=batch, scenario_mode=mode)
     Y = ybus_of(net)
     t0 = time.perf_counter()
     for b in idx:
@@ -87,7 +90,7 @@ def _oracle_worker(args):
     return len(idx), time.perf_counter() - t0
 
 
-def cpu_baseline(name, batch, budget_s):
+def cpu_baseline(name, batch, budget_s, mode="lognormal"):
     """The oracle (dense FP64 Newton, one scenario per task) on the host's
     cores, one BLAS thread per worker process."""
     import multiprocessing as mp
@@ -97,14 +100,14 @@ def cpu_baseline(name, batch, budget_s):
         os.environ[k] = "1"
     ctx = mp.get_context("spawn")
     # calibrate on a few scenarios, then size the sample to the time budget
-    n0, t0 = _oracle_worker((name, batch, list(range(min(8, batch)))))
+    n0, t0 = _oracle_worker((name, batch, list(range(min(8, batch))), mode))
     per = t0 / max(n0, 1)
     n = int(min(batch, max(cores, budget_s * cores / max(per, 1e-6))))
     idx = np.unique(np.linspace(0, batch - 1, n).astype(int)).tolist()
     chunks = [idx[i::cores] for i in range(cores) if idx[i::cores]]
     t = time.perf_counter()
     with ctx.Pool(len(chunks)) as pool:
-        res = pool.map(_oracle_worker, [(name, batch, c) for c in chunks])
+        res = pool.map(_oracle_worker, [(name, batch, c, mode) for c in chunks])
     wall = time.perf_counter() - t
     solved = sum(r[0] for r in res)
     # the workers' set-up (grid generation, Y_bus) is inside the wall time;
@@ -128,7 +131,7 @@ def main():
     from paper_2606_07099_amd import PFTemplate, PFLayer
 
     name = args.workload
-    spec, net, sc = make_case(name)
+    spec, net, sc = make_case(name, scenario_mode=args.scenarios)
     B = sc.batch
     dev = torch.device("cuda:0")
     d = {k: torch.as_tensor(getattr(sc, k), device=dev) for k in ("pd", "qd", "pg", "vset")}
@@ -147,8 +150,8 @@ def main():
     # both completion steps (Step 2 recovers the generation block) under a
     # loss that adds a generation cost and a reactive-reserve penalty
     layerc = PFLayer(tpllay, recover=True)
-    slack_mask = torch.as_tensor(net.bus_type == 2, device=dev)
-    gen_mask = torch.as_tensor(net.bus_type != 0, device=dev)
+    slack_w = torch.as_tensor((net.bus_type == 2).astype(np.float64), device=dev)
+    gen_w = torch.as_tensor((net.bus_type != 0).astype(np.float64), device=dev)
     info64, infomp = tpl64.info(), tplmp.info()
 
     out64 = [torch.empty((B, net.n_bus), dtype=torch.float64, device=dev) for _ in range(2)] + \
@@ -171,7 +174,7 @@ def main():
             v.grad = None
         vm, va, po, qo = layerc(leaves["pd"], leaves["qd"], leaves["pg"], leaves["vset"])
         L = ((torch.relu(vm - 1.05) ** 2).sum() + (torch.relu(0.95 - vm) ** 2).sum() + 0.1 * (va ** 2).sum()
-             + (po[:, slack_mask] ** 2).sum() + 0.5 * (qo[:, gen_mask] ** 2).sum())
+             + ((po * slack_w) ** 2).sum() + 0.5 * ((qo * gen_w) ** 2).sum())
         L.backward()
 
     if args.copy_reference_mib:
@@ -240,10 +243,12 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+f32",
-        "data": "synthetic (seeded meshed grid and lognormal load scenarios)",
+        "data": ("synthetic (seeded meshed grid and lognormal load scenarios)" if args.scenarios == "lognormal"
+                 else "synthetic (seeded meshed grid, uniform +-10% P and Q load perturbations)"),
         "config": {"workload": f"{spec.n_bus}-bus synthetic meshed grid, batch {B}, tol {spec.tol:g}",
                    "n_bus": spec.n_bus, "n_pv": spec.n_pv, "n_branch": spec.n_branch,
-                   "batch": B, "tol": spec.tol, "refine_steps": 2, "parallelism": "single GPU"},
+                   "batch": B, "tol": spec.tol, "refine_steps": 2, "scenarios": args.scenarios,
+                   "parallelism": "single GPU"},
         "fp64_solves_per_s": B / t64.mean(),
         "mixed_solves_per_s": mp_rate,
         "layer_fwd_bwd_samples_per_s": B / tfb.mean(),
@@ -267,13 +272,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(name)
-                                 if B == SPECS[name].batch else None),
+                                 if B == SPECS[name].batch and args.scenarios == "lognormal" else None),
                      "kernel_source_sha256": kernel_source_hash()[:16],
                      "kernel": "k_newton<float> (mixed-precision Newton, one launch per solve)",
                      "bytes_per_launch": bytes_launch, "avg_launch_ms": 1e3 * tmp.mean()},
     }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(name, B, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(name, B, args.cpu_seconds, args.scenarios)
     print(json.dumps(res), flush=True)
 
 

@@ -152,6 +152,27 @@ def test_mixed_adaptive_and_unrefined_match_oracle(name, refine, adaptive, n_che
     assert np.all(res[4].cpu().numpy() < tol)
 
 
+@pytest.mark.parametrize("name,precision,refine,adaptive,n_check",
+                         [("c1", "fp64", 2, False, 48), ("c1", "mixed", 2, False, 48),
+                          ("c1", "mixed", 0, False, 48), ("c3", "mixed", 2, True, 12),
+                          ("c2", "fp64", 2, False, 4), ("c2", "mixed", 0, False, 4)])
+def test_paper_uniform_perturbation_scenarios_match_oracle(name, precision, refine, adaptive, n_check,
+                                                            device):
+    """The paper's own scenario set: independent uniform +-10% perturbations
+    of every PQ load's P and Q (eq. pdqd_perturb).  FP64 to the exact bar,
+    the mixed-precision variants with at most one extra update."""
+    import torch
+    spec, net, sc, tpl, d, tol = make_gpu_case(name, device, precision=precision, refine_steps=refine,
+                                               refine_adaptive=adaptive, scenario_mode="uniform10",
+                                               batch=256 if name == "c2" else None)
+    res = tpl.solve(d["pd"], d["qd"], d["pg"], d["vset"])
+    torch.cuda.synchronize()
+    which = np.unique(np.linspace(0, sc.batch - 1, n_check).astype(int))
+    oracle = newton_batch(ybus_of(net), net.bus_type, sc, tol=tol, which=which)
+    _check_solution(net, sc, which, res, oracle, tol, iters_slack=0 if precision == "fp64" else 1)
+    assert np.all(res[3].cpu().numpy() == 0)
+
+
 def test_large_grid_solution_satisfies_the_equations(device):
     """9241-bus grid, batch 256: every scenario converges and the oracle's own
     mismatch at the returned voltages is below the tolerance (a property that
