@@ -332,17 +332,24 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   // level metadata in chunks of whole rows: read in place from the LDS image
   // by LDS-resident slices, staged chunk by chunk in LDS by HBM-resident ones
   sable::LevelChunks chunks;
-  // HBM-resident slices stage metadata chunks and may keep the tail in LDS:
-  // shrink the chunk budget (not below 2048 words) so that both fit
+  // HBM-resident slices of S scenarios: S as large as keeps at least one
+  // slice per compute unit and leaves room in LDS for the tail copy (its
+  // tail-column blocks, pivot inverses and right-hand sides) and at least
+  // 2048 words of staged metadata; the chunk budget takes what remains.
+  // S = 1 always fits: the tail holds at most 32 x 32 blocks.
   const int n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  auto tail_bytes = [&](int sl) {
+    return (size_t)sl * tsz * (4 * S.tail_cblk.size() + 6 * (size_t)S.tail_t);
+  };
   int hbm_slice = 1;
   while (hbm_slice < sable::kMaxSlice && batch / (2 * hbm_slice) >= n_cu) hbm_slice *= 2;
-  const size_t hbm_tail_bytes = (size_t)hbm_slice * tsz * (4 * S.tail_cblk.size() + 6 * (size_t)S.tail_t);
-  int32_t budget = kChunkInts;
-  if (S.tail_t > 0 && sable::kScratchBytes + hbm_tail_bytes + 4 * 2048 <= max_lds) {
-    const size_t room = (max_lds - sable::kScratchBytes - hbm_tail_bytes) / 4;
-    budget = (int32_t)std::min<size_t>(kChunkInts, room / 4 * 4);
+  while (hbm_slice > 1 && sable::kScratchBytes + tail_bytes(hbm_slice) + 4 * 2048 > max_lds) hbm_slice /= 2;
+  if (sable::kScratchBytes + tail_bytes(hbm_slice) + 4 * 2048 > max_lds) {
+    delete t;
+    return fail(PF_EINVAL, "pf_template_build: the dense tail does not fit in LDS");
   }
+  const size_t room = (max_lds - sable::kScratchBytes - tail_bytes(hbm_slice)) / 4;
+  const int32_t budget = (int32_t)std::min<size_t>(kChunkInts, room / 4 * 4);
   rc = sable::build_level_chunks(S, budget, chunks, err);
   if (rc != 0) { delete t; return fail(PF_EINVAL, err); }
   so.bus_type = (int)pk.add(S.bus_type); so.bus_blk = (int)pk.add(S.bus_blk);
@@ -363,15 +370,8 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   so.adj_bytes = (int)pk.align();
   so.tail_cblk = (int)pk.add(S.tail_cblk); so.tail_lbase = (int)pk.add(S.tail_lbase);
   so.tail_cpos = (int)pk.add(S.tail_cpos);
-  so.task_ptr = (int)pk.add(S.task_ptr);
-  so.task4 = (int)pk.add(S.task4); so.step4 = (int)pk.add(S.step4);
-  so.step_ts = (int)pk.add(S.step_ts); so.upd_tgt = (int)pk.add(S.upd_tgt);
-  so.lev_l_ptr = (int)pk.add(S.lev_l_ptr); so.lev_l_rows = (int)pk.add(S.lev_l_rows);
-  so.lev_um_ptr = (int)pk.add(S.lev_um_ptr); so.lev_um_rows = (int)pk.add(S.lev_um_rows);
+  so.upd_tgt = (int)pk.add(S.upd_tgt);
   so.tk_ptr = (int)pk.add(S.tk_ptr); so.tstep4 = (int)pk.add(S.tstep4);
-  so.lev_u_ptr = (int)pk.add(S.lev_u_ptr); so.lev_u_rows = (int)pk.add(S.lev_u_rows);
-  so.blk_bus = (int)pk.add(S.blk_bus); so.lu_src = (int)pk.add(S.lu_src);
-  so.mirror = (int)pk.add(S.mirror);
   so.ord_p = (int)pk.add(ord_p); so.ord_q = (int)pk.add(ord_q);
   so.total_bytes = (int)pk.align();
   sable::Dims& dm = t->dims;
@@ -385,7 +385,6 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   dm.nch_bs = (int)chunks.bs_ptr.size() - 1;
   dm.chunk_ints = chunks.max_ints;
   dm.tail_nblk = (int)S.tail_cblk.size();
-  dm.tail_lds = 0;
   dm.nch_ut = (int)chunks.ut_ptr.size() - 1;
   dm.nch_lt = (int)chunks.lt_ptr.size() - 1;
 
@@ -420,6 +419,9 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
       const size_t need = sable::kScratchBytes + (size_t)so.adj_bytes + sl * per_adj;
       if (need <= max_lds) { t->adj_slice = sl; t->adj_nt = sable::kResThreads; t->adj_lds = need; break; }
     }
+    // no LDS-resident adjoint slice fits: both run HBM-resident, where the
+    // adjoint reads the forward solve's slice workspace in place
+    if (t->adj_slice == 0) best_s = 0;
   }
   if (best_s > 0) {
     t->lds_res = true;
@@ -432,12 +434,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     t->lds_res = false;
     const int sl = hbm_slice;
     t->slice = sl;
-    t->lds_bytes = sable::kScratchBytes + 4 * (size_t)chunks.max_ints;
-    // the tail (its tail-column blocks and pivot inverses) in LDS when it fits
-    if (S.tail_t > 0 && t->lds_bytes + hbm_tail_bytes <= max_lds) {
-      t->dims.tail_lds = 1;
-      t->lds_bytes += hbm_tail_bytes;
-    }
+    t->lds_bytes = sable::kScratchBytes + 4 * (size_t)chunks.max_ints + tail_bytes(sl);
     // the adjoint reads this slice workspace in place
     t->adj_slice = -sl;
     t->adj_nt = std::min(512, std::max(256, 64 * sl));

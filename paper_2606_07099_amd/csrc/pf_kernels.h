@@ -45,10 +45,8 @@ struct SymOffsets {
   int ut_ptr, ut_blob, lt_ptr, lt_blob, tt_ptr, tt_pairs, y_tr;
   int adj_bytes;
   int tail_cblk, tail_lbase, tail_cpos;   // compact tail numbering (LDS copy of the tail)
-  int task_ptr, task4, step4, step_ts, upd_tgt;
-  int lev_l_ptr, lev_l_rows, lev_um_ptr, lev_um_rows, tk_ptr, tstep4;
-  int lev_u_ptr, lev_u_rows;
-  int blk_bus, lu_src, mirror, ord_p, ord_q;
+  int upd_tgt, tk_ptr, tstep4;            // per-pivot step lists of the tail (LDS tail copy)
+  int ord_p, ord_q;                       // paper-order positions (exports)
   int total_bytes;
 };
 
@@ -60,8 +58,7 @@ struct Dims {
   int nch_f, nch_fs, nch_bs;      // metadata chunks of the factor, forward and backward levels
   int nch_ut, nch_lt;             // metadata chunks of the transposed solves
   int chunk_ints;                 // largest chunk (int32 words), staged after the LDS scratch
-  int tail_nblk;                  // tail blocks in tail columns
-  int tail_lds;                   // HBM slices: 1 if the tail is factored and solved in an LDS copy
+  int tail_nblk;                  // blocks of the tail rows in tail columns (LDS tail copy)
 };
 
 // Offsets of the per-scenario arrays, in elements.  FP64 arrays:
@@ -109,7 +106,7 @@ hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int 
                          bool lds_res, hipStream_t st);
 // slice > 0: LDS-resident adjoint slices of that width (256 threads);
 // slice < 0: HBM-resident slices of width -slice reading the forward solve's
-// slice workspace (at most 512 threads); 0: one scenario per workgroup
+// slice workspace (at most 512 threads)
 hipError_t launch_adjoint(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds, hipStream_t st);
 hipError_t launch_jacobian_dense(const KParams& kp, int grid, hipStream_t st);
 // Step-2 recovery of the generation block for kp.count scenarios

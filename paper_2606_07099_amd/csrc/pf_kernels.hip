@@ -55,13 +55,12 @@ struct Sym {
   const int *bus_type, *bus_blk, *y_rp, *y_ci;
   const double *y_g, *y_b;
   const int *rp, *ci, *diag;
-  const int4 *fill4, *task4, *step4;
-  const int *task_ptr, *step_ts, *upd_tgt;
-  const int *lev_l_ptr, *lev_l_rows, *lev_u_ptr, *lev_u_rows;
-  const int *lev_um_ptr, *lev_um_rows, *tail_pos, *tail_split, *tk_ptr;
+  const int4* fill4;
+  const int* upd_tgt;
+  const int *tail_pos, *tail_split, *tk_ptr;
   const int4* tstep4;
   const unsigned* tail_mask;
-  const int *blk_bus, *lu_src, *mirror, *y_tr, *ord_p, *ord_q;
+  const int *y_tr, *ord_p, *ord_q;
   const int *f_ptr, *f_blob, *fs_ptr, *fs_blob, *bs_ptr, *bs_blob;
   const int *tail_cblk, *tail_lbase, *tail_cpos;
 };
@@ -89,22 +88,9 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
   m.fs_blob = I(nb, o.fs_blob);
   m.bs_ptr = I(nb, o.bs_ptr);
   m.bs_blob = I(nb, o.bs_blob);
-  m.task_ptr = I(g, o.task_ptr);
-  m.task4 = reinterpret_cast<const int4*>(g + o.task4);
-  m.step4 = reinterpret_cast<const int4*>(g + o.step4);
-  m.step_ts = I(g, o.step_ts);
   m.upd_tgt = I(g, o.upd_tgt);
-  m.lev_l_ptr = I(g, o.lev_l_ptr);
-  m.lev_l_rows = I(g, o.lev_l_rows);
-  m.lev_um_ptr = I(g, o.lev_um_ptr);
-  m.lev_um_rows = I(g, o.lev_um_rows);
   m.tk_ptr = I(g, o.tk_ptr);
   m.tstep4 = reinterpret_cast<const int4*>(g + o.tstep4);
-  m.lev_u_ptr = I(g, o.lev_u_ptr);
-  m.lev_u_rows = I(g, o.lev_u_rows);
-  m.blk_bus = I(g, o.blk_bus);
-  m.lu_src = I(g, o.lu_src);
-  m.mirror = I(g, o.mirror);
   m.y_tr = I(g, o.y_tr);   // LDS-resident adjoint slices rebind it to their LDS copy
   m.ord_p = I(g, o.ord_p);
   m.ord_q = I(g, o.ord_q);
@@ -471,65 +457,9 @@ __device__ __forceinline__ void phase_solve(const Sym& m, const Dims& D, St<T>& 
   }
 }
 
-// U^T w = g (in place in y) by L-levels: w_a = U_aa^-T (g_a - sum_k U_ka^T w_k)
-template <typename T>
-__device__ __forceinline__ void phase_ut_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
-  for (int lev = 0; lev < D.nlev_l; ++lev) {
-    const int r0 = m.lev_l_ptr[lev], r1 = m.lev_l_ptr[lev + 1];
-    const Grp g = groups(r1 - r0, tid, nt, gmin);
-    const int G = g.G, lane = g.lane;
-    for (int ri = r0 + g.gid; ri < r1; ri += g.ng) {
-      const int a = m.lev_l_rows[ri];
-      T s0 = T(0), s1 = T(0);
-      for (int p = m.rp[a] + lane; p < m.diag[a]; p += G) {
-        const Blk<T> U = ld_blk(c.lu + 4 * m.mirror[p]);  // U_ka, k = ci[p]
-        const int k = m.ci[p];
-        const T w0 = c.y[2 * k], w1 = c.y[2 * k + 1];
-        s0 += U.a * w0 + U.c * w1;
-        s1 += U.b * w0 + U.d * w1;
-      }
-      s0 = group_sum<T, 1>(s0, G);
-      s1 = group_sum<T, 1>(s1, G);
-      if (lane == 0) {
-        const Blk<T> Di = ld_blk(c.dinv + 4 * a);
-        const T t0 = c.y[2 * a] - s0, t1 = c.y[2 * a + 1] - s1;
-        c.y[2 * a] = Di.a * t0 + Di.c * t1;
-        c.y[2 * a + 1] = Di.b * t0 + Di.d * t1;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// L^T l = w (in place in y) by U-levels: l_a = w_a - sum_j L_ja^T l_j
-template <typename T>
-__device__ __forceinline__ void phase_lt_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin) {
-  for (int lev = 0; lev < D.nlev_u; ++lev) {
-    const int r0 = m.lev_u_ptr[lev], r1 = m.lev_u_ptr[lev + 1];
-    const Grp g = groups(r1 - r0, tid, nt, gmin);
-    const int G = g.G, lane = g.lane;
-    for (int ri = r0 + g.gid; ri < r1; ri += g.ng) {
-      const int a = m.lev_u_rows[ri];
-      T s0 = T(0), s1 = T(0);
-      for (int p = m.diag[a] + 1 + lane; p < m.rp[a + 1]; p += G) {
-        const Blk<T> L = ld_blk(c.lu + 4 * m.mirror[p]);  // L_ja, j = ci[p]
-        const int j = m.ci[p];
-        const T l0 = c.y[2 * j], l1 = c.y[2 * j + 1];
-        s0 += L.a * l0 + L.c * l1;
-        s1 += L.b * l0 + L.d * l1;
-      }
-      s0 = group_sum<T, 1>(s0, G);
-      s1 = group_sum<T, 1>(s1, G);
-      if (lane == 0) { c.y[2 * a] -= s0; c.y[2 * a + 1] -= s1; }
-    }
-    __syncthreads();
-  }
-}
-
 // ----------------------------------------------------------------------------
 // dense tail: the top rows of the elimination tree, one wavefront per
-// scenario, ordered by the in-order completion of a wavefront's memory
-// operations (no workgroup barrier inside)
+// scenario, with no workgroup barrier inside
 
 __device__ __forceinline__ double lane_bcast(double v, int l) {
   const long long b = __double_as_longlong(v);
@@ -539,137 +469,6 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
 }
 __device__ __forceinline__ float lane_bcast(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
-// LU of the tail rows, one pivot at a time in row order: the pivot block is
-// inverted, then every tail row with a multiplier for this pivot forms it,
-// applies it to its right-hand side entry and to its targets of the pivot's
-// U row, lanes = (elimination step, entry of the U row).  Same arithmetic as
-// the barrier-synchronised tasks, one pivot per wavefront step.
-template <typename T, int S, bool RES>
-__device__ __forceinline__ void phase_tail_factor(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, bool fwd,
-                                  int* piv) {
-  const int t = D.tail_t, tb = D.tail_base;
-  const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
-  for (int s = w; s < S; s += nw) {
-    for (int k = 0; k < t; ++k) {
-      const int ak = tb + k;
-      const int dk = m.diag[ak];
-      Blk<T> Di = {T(0), T(0), T(0), T(0)};
-      if (l == 0) {
-        const Blk<T> Dk = ld_blk(c.lu + sB<S>(dk, s));
-        const T det = Dk.a * Dk.d - Dk.b * Dk.c;
-        const T inv = recip(det);
-        Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
-        // pivots of the block: a, then the Schur complement d - c b / a
-        const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
-        const bool zero = !(fabs(Dk.a) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
-                          !(fabs(det) > eps * fabs(Dk.a) * (fabs(Dk.c) + fabs(Dk.d))) ||
-                          !isfinite(inv);
-        if (zero) piv[s] = 1;
-        st_blk(c.dinv + sB<S>(ak, s), Di);
-      }
-      Di = {lane_bcast(Di.a, 0), lane_bcast(Di.b, 0), lane_bcast(Di.c, 0), lane_bcast(Di.d, 0)};
-      const int t0 = m.tk_ptr[k], t1 = m.tk_ptr[k + 1];
-      if (t1 > t0) {
-        T yk0 = T(0), yk1 = T(0);
-        if (fwd) { yk0 = c.y[sP<S>(ak, s)]; yk1 = c.y[sP<S>(ak, s) + 1]; }
-        const int ks = dk + 1, n = m.rp[ak + 1] - ks;
-        int E = 1;
-        while (E < n && E < 64) E <<= 1;
-        const int lg = __builtin_ctz(E), per = 64 >> lg;
-        const int e = l & (E - 1);
-        for (int st = t0 + (l >> lg); st - (l >> lg) < t1; st += per) {
-          if (st >= t1) continue;
-          const int4 r = m.tstep4[st];   // row i, q, first target, -
-          const int rs = m.rp[r.x];
-          T* W = c.lu + sB<S>(rs, 0);
-          const Blk<T> L = mul(ld_blk(W + sB<S>(r.y, s)), Di);
-          for (int j = e; j < n; j += E) {
-            const Blk<T> U = ld_blk(c.lu + sB<S>(ks + j, s));
-            T* a = W + sB<S>(m.upd_tgt[r.z + j], s);
-            Blk<T> x = ld_blk(a);
-            const Blk<T> LU = mul(L, U);
-            x.a -= LU.a; x.b -= LU.b; x.c -= LU.c; x.d -= LU.d;
-            st_blk(a, x);
-          }
-          if (e == 0) {
-            st_blk(W + sB<S>(r.y, s), L);
-            if (fwd) {
-              c.y[sP<S>(r.x, s)] -= L.a * yk0 + L.b * yk1;
-              c.y[sP<S>(r.x, s) + 1] -= L.c * yk0 + L.d * yk1;
-            }
-          }
-        }
-      }
-      wave_order<RES>();
-    }
-  }
-}
-
-// forward solve of the tail rows: their terms on rows outside the tail,
-// then the unit block-lower tail block, broadcasting each finished unknown
-template <typename T, int S, bool RES>
-__device__ __forceinline__ void phase_tail_fsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
-  const int t = D.tail_t, tb = D.tail_base;
-  const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
-  for (int s = w; s < S; s += nw) {
-    T y0 = T(0), y1 = T(0);
-    if (l < t) {
-      const int a = tb + l;
-      y0 = c.y[sP<S>(a, s)];
-      y1 = c.y[sP<S>(a, s) + 1];
-      for (int p = m.rp[a]; p < m.tail_split[l]; ++p) {
-        const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
-        const int k = m.ci[p];
-        const T z0 = c.y[sP<S>(k, s)], z1 = c.y[sP<S>(k, s) + 1];
-        y0 -= L.a * z0 + L.b * z1;
-        y1 -= L.c * z0 + L.d * z1;
-      }
-    }
-    for (int j = 0; j < t; ++j) {
-      const T yj0 = lane_bcast(y0, j), yj1 = lane_bcast(y1, j);
-      if (l > j && l < t) {
-        const int p = m.tail_pos[l * t + j];
-        if (p >= 0) {
-          const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
-          y0 -= L.a * yj0 + L.b * yj1;
-          y1 -= L.c * yj0 + L.d * yj1;
-        }
-      }
-    }
-    if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
-  }
-}
-
-// backward solve of the tail block (its rows only couple to tail columns):
-// the last unknown first, each finished one broadcast to the rows above
-template <typename T, int S, bool RES>
-__device__ __forceinline__ void phase_tail_bsolve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
-  const int t = D.tail_t, tb = D.tail_base;
-  const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
-  for (int s = w; s < S; s += nw) {
-    T y0 = T(0), y1 = T(0);
-    if (l < t) { y0 = c.y[sP<S>(tb + l, s)]; y1 = c.y[sP<S>(tb + l, s) + 1]; }
-    for (int j = t - 1; j >= 0; --j) {
-      if (l == j) {
-        const Blk<T> Di = ld_blk(c.dinv + sB<S>(tb + j, s));
-        const T x0 = Di.a * y0 + Di.b * y1, x1 = Di.c * y0 + Di.d * y1;
-        y0 = x0;
-        y1 = x1;
-      }
-      const T xj0 = lane_bcast(y0, j), xj1 = lane_bcast(y1, j);
-      if (l < j) {
-        const int p = m.tail_pos[l * t + j];
-        if (p >= 0) {
-          const Blk<T> U = ld_blk(c.lu + sB<S>(p, s));
-          y0 -= U.a * xj0 + U.b * xj1;
-          y1 -= U.c * xj0 + U.d * xj1;
-        }
-      }
-    }
-    if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
-  }
 }
 
 // ----------------------------------------------------------------------------
@@ -1092,54 +891,6 @@ struct GenW {
   }
 };
 
-// adjoint residual r = g - J1^T lam in FP64 without forming J1 (transposed
-// directional derivative of S = V conj(Y V)): with nu = lam_P + j lam_Q and
-// c_m = conj(nu_m I_m) + sum_i Y_im nu_i conj(V_i),
-//   (J1^T lam)_theta_m = Im(V_m c_m),  (J1^T lam)_|V|m = -Re(V_m c_m) / |V_m|.
-// Also stores Re(V_m c_m) / |V_m| = -(J3^T lam)_m for every bus in aux.
-// g == nullptr: only aux is produced.  One scenario (HBM state).
-template <typename T>
-__device__ __forceinline__ void phase_adj_residual(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
-                                   const double* lam, double* g, bool to_y, GenW gw = GenW{}) {
-  for (int i = tid; i < D.n_bus; i += nt) {   // w_i = nu_i conj(V_i) -> (dvr, dvi)
-    const int a = m.bus_blk[i];
-    double nr = 0.0, ni = 0.0;
-    if (a >= 0 && lam) { nr = lam[2 * a]; ni = m.bus_type[i] == 0 ? lam[2 * a + 1] : 0.0; }
-    gw.add(i, 0, m.bus_type[i], nr, ni);
-    c.dvr[i] = nr * c.e[i] + ni * c.f[i];
-    c.dvi[i] = ni * c.e[i] - nr * c.f[i];
-  }
-  __syncthreads();
-  for (int mb = tid; mb < D.n_bus; mb += nt) {
-    double tr = 0.0, ti = 0.0;
-    for (int q = m.y_rp[mb]; q < m.y_rp[mb + 1]; ++q) {
-      const int i = m.y_ci[q];
-      const int qt = m.y_tr[q];              // position of Y_im
-      const double yg = m.y_g[qt], yb = m.y_b[qt];
-      tr += yg * c.dvr[i] - yb * c.dvi[i];
-      ti += yg * c.dvi[i] + yb * c.dvr[i];
-    }
-    const int a = m.bus_blk[mb];
-    double nr = 0.0, ni = 0.0;
-    if (a >= 0 && lam) { nr = lam[2 * a]; ni = m.bus_type[mb] == 0 ? lam[2 * a + 1] : 0.0; }
-    gw.add(mb, 0, m.bus_type[mb], nr, ni);
-    const double ir = c.ire[mb], ii = c.iim[mb];
-    const double cr = (nr * ir - ni * ii) + tr;      // Re c_m
-    const double ci = -(nr * ii + ni * ir) + ti;     // Im c_m
-    const double e = c.e[mb], f = c.f[mb];
-    const double vcr = e * cr - f * ci;               // Re(V_m c_m)
-    const double vci = e * ci + f * cr;               // Im(V_m c_m)
-    c.aux[mb] = vcr / c.vm[mb];
-    if (a >= 0 && g) {
-      const double r0 = g[2 * a] - vci;
-      const double r1 = m.bus_type[mb] == 0 ? g[2 * a + 1] + vcr / c.vm[mb] : 0.0;
-      if (to_y) { c.y[2 * a] = T(r0); c.y[2 * a + 1] = T(r1); }
-      else { g[2 * a] = r0; g[2 * a + 1] = r1; }   // in place: g + (transposed product)
-    }
-  }
-  __syncthreads();
-}
-
 // e + jf from (|V|, theta) for the scenarios in `mask`
 template <typename T, int S>
 __device__ __forceinline__ void phase_set_state(const Dims& D, St<T>& c, int tid, int nt, int mask) {
@@ -1230,7 +981,6 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
   T* tl = reinterpret_cast<T*>(smem + kScratchBytes + 4 * (size_t)kp.dims.chunk_ints);   // HBM: LDS tail
   T* td = tl + (size_t)kp.dims.tail_nblk * S * 4;
   T* ty = td + (size_t)kp.dims.tail_t * S * 4;
-  const bool ltail = !RES && kp.dims.tail_lds;
   TailRow<T> R;                             // this wavefront's factored tail rows
   while (true) {
     phase_mismatch<T, S>(m, D, c, tid, nt, scr);
@@ -1254,12 +1004,10 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
     phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, true, piv, stg);
     if constexpr (RES) {
       if (wv < S) rt_factor<T, S>(m, D, c, wv, ln, true, piv, R);
-    } else if (ltail) {
+    } else {
       ltail_copy<T, S>(m, D, c, tl, tid, nt, false);
       __syncthreads();
       ltail_factor<T, S>(m, D, c, tl, td, ty, tid, nt, true, piv);
-    } else {
-      phase_tail_factor<T, S, RES>(m, D, c, tid, nt, true, piv);
     }
     __syncthreads();
     for (int s = 0; s < S; ++s)
@@ -1270,10 +1018,8 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
     if (!act) break;
     if constexpr (RES) {
       if (wv < S) rt_bsolve<T, S>(m, D, c, wv, ln, R);
-    } else if (ltail) {
-      ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt);
     } else {
-      phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
+      ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt);
     }
     __syncthreads();
     phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg);
@@ -1300,14 +1046,10 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
             rt_fsolve<T, S>(m, D, c, wv, ln, R);
             rt_bsolve<T, S>(m, D, c, wv, ln, R);
           }
-        } else if (ltail) {
+        } else {
           ltail_fsolve<T, S>(m, D, c, tl, tid, nt);
           __syncthreads();
           ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt);
-        } else {
-          phase_tail_fsolve<T, S, RES>(m, D, c, tid, nt);
-          __syncthreads();
-          phase_tail_bsolve<T, S, RES>(m, D, c, tid, nt);
         }
         __syncthreads();
         phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg);
@@ -1376,15 +1118,13 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
         rt_factor<T, S>(m, D, c, wv, ln, false, piv, R);
         rt_store<T, S>(m, D, c, wv, ln, R);
       }
-    } else if (ltail) {
+    } else {
       ltail_copy<T, S>(m, D, c, tl, tid, nt, false);
       __syncthreads();
       ltail_factor<T, S>(m, D, c, tl, td, ty, tid, nt, false, piv);
       __syncthreads();
       ltail_copy<T, S>(m, D, c, tl, tid, nt, true);
       ltail_store_dinv<T, S>(D, c, td, tid, nt);
-    } else {
-      phase_tail_factor<T, S, RES>(m, D, c, tid, nt, false, piv);
     }
     __syncthreads();
     if (tid < S && s_st[tid] == 0 && piv[tid]) s_st[tid] = 3;
@@ -1427,110 +1167,15 @@ __device__ __forceinline__ void gen_direct(const KParams& kp, size_t o, int bt, 
 }
 
 // ----------------------------------------------------------------------------
-// adjoint kernel (one scenario per workgroup, HBM-resident state and factors)
-
-template <typename T>
-__global__ void __launch_bounds__(1024) k_adjoint(KParams kp) {
-  const Dims& D = kp.dims;
-  const Sym m = bind_sym(kp.sym, kp.sym, kp.so);
-  const int b = blockIdx.x;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  St<T> c = bind_state<T, 1>(kp.ws_d + (size_t)b * kp.lay.sd,
-                             reinterpret_cast<T*>(kp.ws_t) + (size_t)b * kp.lay.st, kp.lay);
-  const int n = D.n_bus, nb = D.nb;
-  const size_t io = (size_t)b * n;
-  const bool ok = kp.ws_i[(size_t)b * 4] == 0;
-  const bool eval = kp.mode == MODE_EVAL_ADJOINT;
-
-  // g_z1 per block: (dL/dtheta, dL/d|V| on PQ) -> F (FP64)
-  for (int i = tid; i < n; i += nt) {
-    const int a = m.bus_blk[i];
-    if (a < 0) continue;
-    double g0, g1;
-    if (eval) {
-      const double* rhs = kp.rhs + (size_t)b * D.nj;
-      g0 = rhs[D.npq + m.ord_p[i]];
-      g1 = m.bus_type[i] == 0 ? rhs[m.ord_q[i]] : 0.0;
-    } else {
-      g0 = kp.g_va[io + i];
-      g1 = m.bus_type[i] == 0 ? kp.g_vm[io + i] : 0.0;
-    }
-    c.F[2 * a] = g0;
-    c.F[2 * a + 1] = g1;
-  }
-  // I at the kept state (needed by the FP64 transposed products)
-  for (int i = tid; i < n; i += nt) {
-    double ir = 0.0, ii = 0.0;
-    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
-      const int j = m.y_ci[q];
-      ir += m.y_g[q] * c.e[j] - m.y_b[q] * c.f[j];
-      ii += m.y_g[q] * c.f[j] + m.y_b[q] * c.e[j];
-    }
-    c.ire[i] = ir;
-    c.iim[i] = ii;
-  }
-  __syncthreads();
-  // Step 2: g_z1 += vbar2 on z1 (vbar2 = -J2^T dL/dz2, a transposed product)
-  GenW gw;
-  if (!eval) { gw.p = kp.g_pgo; gw.q = kp.g_qgo; gw.b0 = b; gw.count = kp.count; gw.n = n; }
-  if (gw.on()) phase_adj_residual<T>(m, D, c, tid, nt, nullptr, c.F, false, gw);
-  for (int q = tid; q < 2 * nb; q += nt) c.y[q] = T(c.F[q]);
-  __syncthreads();
-  phase_ut_solve<T>(m, D, c, tid, nt, 1);
-  phase_lt_solve<T>(m, D, c, tid, nt, 1);
-  for (int q = tid; q < 2 * nb; q += nt) c.dx[q] = double(c.y[q]);
-  __syncthreads();
-  if (sizeof(T) == 4) {
-    for (int r = 0; r < kp.refine; ++r) {
-      phase_adj_residual<T>(m, D, c, tid, nt, c.dx, c.F, true);
-      phase_ut_solve<T>(m, D, c, tid, nt, 1);
-      phase_lt_solve<T>(m, D, c, tid, nt, 1);
-      for (int q = tid; q < 2 * nb; q += nt) c.dx[q] += double(c.y[q]);
-      __syncthreads();
-    }
-  }
-  if (eval) {
-    if (b < kp.count) {
-      double* o = kp.out + (size_t)b * D.nj;
-      for (int i = tid; i < n; i += nt) {
-        const int a = m.bus_blk[i];
-        if (a < 0) continue;
-        o[m.ord_p[i]] = c.dx[2 * a];
-        if (m.bus_type[i] == 0) o[D.npvpq + m.ord_q[i]] = c.dx[2 * a + 1];
-      }
-    }
-    return;
-  }
-  // J3^T lam via the transposed product at the solution (-(J3^T lam) lands in aux)
-  // (with Step-2 weights the same product also carries vbar2 on |V| of x)
-  phase_adj_residual<T>(m, D, c, tid, nt, c.dx, nullptr, false, gw);
-  for (int i = tid; i < n; i += nt) {
-    const int a = m.bus_blk[i];
-    const int bt = m.bus_type[i];
-    double gpd = 0.0, gqd = 0.0, gpg = 0.0, gvs = 0.0;
-    if (ok) {
-      if (a >= 0) {
-        gpd = c.dx[2 * a];
-        if (bt == 0) gqd = c.dx[2 * a + 1];
-        if (bt == 1) gpg = -c.dx[2 * a];
-      }
-      if (bt != 0) gvs = kp.g_vm[io + i] + c.aux[i];
-      gen_direct(kp, io + i, bt, gpd, gqd, gpg);
-    }
-    if (kp.g_pd) kp.g_pd[io + i] = gpd;
-    if (kp.g_qd) kp.g_qd[io + i] = gqd;
-    if (kp.g_pg) kp.g_pg[io + i] = gpg;
-    if (kp.g_vset) kp.g_vset[io + i] = gvs;
-  }
-}
-
-// ----------------------------------------------------------------------------
 // adjoint slices: S scenarios per workgroup.  LDS-resident (small grids):
 // the kept state and factors copied into LDS, level metadata chunks in place
 // in the LDS image.  HBM-resident: the slice workspace of the forward solve
 // (state and factors interleaved by scenario) read in place, metadata chunks
 // staged in LDS.  The transposed dense tail in registers, one wavefront per
-// scenario.  Same arithmetic as k_adjoint.
+// scenario.  U^T then L^T with the kept factors (transposed blocks read
+// through the mirror-position map), FP64-residual refinement for FP32
+// factors, then the gradient assembly with J3^T lambda (and vbar2) as one
+// transposed product through Y_bus.
 
 // metadata of the transposed solves
 struct AdjSym {
@@ -1650,8 +1295,14 @@ __device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const D
   if (l < t) c.y[sP<S>(tb + l, s) + h] = y;
 }
 
-// the adjoint residual g - J1^T lam (and -(J3^T lam) in aux) on an interleaved
-// slice: as phase_adj_residual
+// adjoint residual r = g - J1^T lam in FP64 without forming J1 (transposed
+// directional derivative of S = V conj(Y V)), on an interleaved slice: with
+// nu = lam_P + j lam_Q (plus the Step-2 weights) and
+// c_m = conj(nu_m I_m) + sum_i Y_im nu_i conj(V_i),
+//   (J1^T lam)_theta_m = Im(V_m c_m),  (J1^T lam)_|V|m = -Re(V_m c_m) / |V_m|.
+// Also stores Re(V_m c_m) / |V_m| = -(J3^T lam)_m for every bus in aux.
+// g == nullptr: only aux; to_y: r into y (factor precision); otherwise r
+// replaces g in place.
 template <typename T, int S>
 __device__ __forceinline__ void phase_adj_residual_s(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
                                                      const double* lam, double* g, bool to_y,
@@ -1984,10 +1635,6 @@ static hipError_t launch_adjoint_hbm_t(const KParams& kp, int slice, int grid, i
 
 template <typename T>
 static hipError_t launch_adjoint_t(const KParams& kp, int slice, int grid, int nt, size_t lds, hipStream_t st) {
-  if (slice == 0) {
-    hipLaunchKernelGGL((k_adjoint<T>), dim3(grid), dim3(nt), 0, st, kp);
-    return hipGetLastError();
-  }
   if (slice < 0) return launch_adjoint_hbm_t<T>(kp, -slice, grid, nt, lds, st);
   if (nt != kResThreads) return hipErrorInvalidValue;
   switch (slice) {
@@ -2048,6 +1695,11 @@ static hipError_t set_lds_t(int max_lds) {
   set(reinterpret_cast<const void*>(&k_adjoint_slice<T, true, 1>));
   set(reinterpret_cast<const void*>(&k_adjoint_slice<T, true, 2>));
   set(reinterpret_cast<const void*>(&k_adjoint_slice<T, true, 4>));
+  set(reinterpret_cast<const void*>(&k_adjoint_slice<T, false, 1>));
+  set(reinterpret_cast<const void*>(&k_adjoint_slice<T, false, 2>));
+  set(reinterpret_cast<const void*>(&k_adjoint_slice<T, false, 4>));
+  set(reinterpret_cast<const void*>(&k_adjoint_slice<T, false, 8>));
+  set(reinterpret_cast<const void*>(&k_adjoint_slice<T, false, 16>));
   return e;
 }
 
