@@ -634,12 +634,13 @@ __device__ __forceinline__ void ltail_bsolve(const Sym& m, const Dims& D, St<T>&
 // register-resident dense tail (LDS-resident slices): wavefront w handles the
 // tail of scenario w.  Lanes 2l and 2l + 1 hold the two scalar rows of tail
 // block row l (components a b, resp. c d, of every 2x2 block), as register
-// vectors indexed with the wavefront-uniform column (register-indexing mode,
-// no scratch): L part left of the diagonal, the inverted pivot block on it, U
-// part right of it.  Pivot blocks, U rows and solved unknowns reach the
-// other lanes by lane broadcast; the structure masks skip the updates of
-// structurally zero blocks.  Same arithmetic, in the same order, as the
-// sparse per-pivot elimination.
+// vectors: L part left of the diagonal, the inverted pivot block on it, U
+// part right of it.  The column loops are unrolled over the register
+// capacity, so each column is a fixed register and a structurally zero block
+// costs one uniform branch (per-pivot structure masks); only the pivot
+// column is indexed at run time (register-indexing mode, no scratch).  Pivot
+// blocks, U rows and solved unknowns reach the other lanes by lane broadcast.
+// Same arithmetic, in the same order, as the sparse per-pivot elimination.
 
 // register capacity of the dense tail, in block rows (one 32-dword register
 // tuple per scalar-row half)
@@ -663,14 +664,20 @@ __device__ __forceinline__ double pair_swap(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// this lane's scalar row of the tail blocks (l, j), j < t, into R
+// this lane's scalar row of the tail blocks (l, j), j < t, into R.  Every
+// register-vector index in the tail code below is a compile-time constant
+// (unrolled column loops with uniform skips), except the pivot column of the
+// factorisation.
 template <typename T, int S>
 __device__ __forceinline__ void rt_load(const Sym& m, const Dims& D, const St<T>& c, int s, int l, int h,
                                         TailRow<T>& R) {
   R = TailRow<T>{};
   const int t = D.tail_t;
+  constexpr int C = tail_cap<T>();
   // eight columns at a time, their index and value loads issued together
-  for (int jb = 0; jb < t; jb += 8) {
+#pragma unroll
+  for (int jb = 0; jb < C; jb += 8) {
+    if (jb >= t) break;
     int p[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -689,8 +696,7 @@ __device__ __forceinline__ void rt_load(const Sym& m, const Dims& D, const St<T>
       }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (jb + u < t) { R.p[jb + u] = x0[u]; R.q[jb + u] = x1[u]; }
+    for (int u = 0; u < 8; ++u) { R.p[jb + u] = x0[u]; R.q[jb + u] = x1[u]; }
   }
 }
 
@@ -719,22 +725,24 @@ __device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c,
     zero |= !(fabs(da) > eps * (fabs(da) + fabs(db))) ||
             !(fabs(det) > eps * fabs(da) * (fabs(dc) + fabs(dd))) || !isfinite(inv);
     const bool below = l > k && l < t;
-    const T l0 = xp * ia + xq * ic, l1 = xp * ib + xq * id;   // row h of A_lk D_k^-1
+    // row h of A_lk D_k^-1 on the rows below the pivot, zero elsewhere, so
+    // that the update below needs no per-lane select
+    const T l0 = below ? xp * ia + xq * ic : T(0), l1 = below ? xp * ib + xq * id : T(0);
     R.p[k] = below ? l0 : (l == k ? (h ? ic : ia) : xp);
     R.q[k] = below ? l1 : (l == k ? (h ? id : ib) : xq);
     if (fwd) {
       const T yk0 = lane_bcast(y, 2 * k), yk1 = lane_bcast(y, 2 * k + 1);
-      if (below) y -= l0 * yk0 + l1 * yk1;
+      y -= l0 * yk0 + l1 * yk1;
     }
-    unsigned mk = __builtin_amdgcn_readfirstlane(m.tail_mask[k]);
-    while (mk) {
-      const int j = __builtin_ctz(mk);
-      mk &= mk - 1;
-      const T zp = R.p[j], zq = R.q[j];
-      const T ua = lane_bcast(zp, 2 * k), ub = lane_bcast(zq, 2 * k);
-      const T uc = lane_bcast(zp, 2 * k + 1), ud = lane_bcast(zq, 2 * k + 1);
-      R.p[j] = below ? zp - (l0 * ua + l1 * uc) : zp;
-      R.q[j] = below ? zq - (l0 * ub + l1 * ud) : zq;
+    const unsigned mk = __builtin_amdgcn_readfirstlane(m.tail_mask[k]);   // U columns j > k
+#pragma unroll
+    for (int j = 0; j < tail_cap<T>(); ++j) {
+      if ((mk >> j) & 1u) {
+        const T ua = lane_bcast(R.p[j], 2 * k), ub = lane_bcast(R.q[j], 2 * k);
+        const T uc = lane_bcast(R.p[j], 2 * k + 1), ud = lane_bcast(R.q[j], 2 * k + 1);
+        R.p[j] -= l0 * ua + l1 * uc;
+        R.q[j] -= l0 * ub + l1 * ud;
+      }
     }
   }
   if (zero && ln == 0) piv[s] = 1;
@@ -748,7 +756,10 @@ __device__ __forceinline__ void rt_store(const Sym& m, const Dims& D, St<T>& c, 
                                          const TailRow<T>& R) {
   const int t = D.tail_t, tb = D.tail_base;
   const int l = ln >> 1, h = ln & 1;
-  for (int jb = 0; jb < t; jb += 8) {
+  constexpr int C = tail_cap<T>();
+#pragma unroll
+  for (int jb = 0; jb < C; jb += 8) {
+    if (jb >= t) break;
     int p[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -758,13 +769,11 @@ __device__ __forceinline__ void rt_store(const Sym& m, const Dims& D, St<T>& c, 
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      if (jb + u < t) {
-        const T xp = R.p[jb + u], xq = R.q[jb + u];
-        T* b = nullptr;
-        if (p[u] == -2) b = c.dinv + sB<S>(tb + l, s) + 2 * h;
-        else if (p[u] >= 0) b = c.lu + sB<S>(p[u], s) + 2 * h;
-        if (b) { b[0] = xp; b[1] = xq; }
-      }
+      const T xp = R.p[jb + u], xq = R.q[jb + u];
+      T* b = nullptr;
+      if (p[u] == -2) b = c.dinv + sB<S>(tb + l, s) + 2 * h;
+      else if (p[u] >= 0) b = c.lu + sB<S>(p[u], s) + 2 * h;
+      if (b) { b[0] = xp; b[1] = xq; }
     }
   }
 }
@@ -787,13 +796,13 @@ __device__ __forceinline__ void rt_fsolve(const Sym& m, const Dims& D, St<T>& c,
       y -= b[0] * c.y[sP<S>(k, s)] + b[1] * c.y[sP<S>(k, s) + 1];
     }
   }
-  unsigned lm = __builtin_amdgcn_readfirstlane(m.tail_mask[t]);
-  while (lm) {
-    const int j = __builtin_ctz(lm);
-    lm &= lm - 1;
-    const T lp = R.p[j], lq = R.q[j];
-    const T yj0 = lane_bcast(y, 2 * j), yj1 = lane_bcast(y, 2 * j + 1);
-    if (l > j && l < t) y -= lp * yj0 + lq * yj1;
+  const unsigned lm = __builtin_amdgcn_readfirstlane(m.tail_mask[t]);   // columns with L blocks
+#pragma unroll
+  for (int j = 0; j < tail_cap<T>(); ++j) {
+    if ((lm >> j) & 1u) {
+      const T yj0 = lane_bcast(y, 2 * j), yj1 = lane_bcast(y, 2 * j + 1);
+      if (l > j && l < t) y -= R.p[j] * yj0 + R.q[j] * yj1;
+    }
   }
   if (l < t) c.y[sP<S>(tb + l, s) + h] = y;
 }
@@ -807,16 +816,19 @@ __device__ __forceinline__ void rt_bsolve(const Sym& m, const Dims& D, St<T>& c,
   const int l = ln >> 1, h = ln & 1;
   T y = T(0);
   if (l < t) y = c.y[sP<S>(tb + l, s) + h];
-  const unsigned cm = __builtin_amdgcn_readfirstlane(m.tail_mask[t + 1]);
-  for (int j = t - 1; j >= 0; --j) {
-    const T xp = R.p[j], xq = R.q[j];
-    // x_j = D_j^-1 y_j on the two lanes of row j: row h of the inverse
-    // times both components (the partner lane holds the other one)
-    const T yo = pair_swap(y);
-    if (l == j) y = xp * (h ? yo : y) + xq * (h ? y : yo);
-    if ((cm >> j) & 1u) {
-      const T xj0 = lane_bcast(y, 2 * j), xj1 = lane_bcast(y, 2 * j + 1);
-      if (l < j) y -= xp * xj0 + xq * xj1;
+  const unsigned cm = __builtin_amdgcn_readfirstlane(m.tail_mask[t + 1]);   // columns with U blocks
+#pragma unroll
+  for (int j = tail_cap<T>() - 1; j >= 0; --j) {
+    if (j < t) {
+      const T xp = R.p[j], xq = R.q[j];
+      // x_j = D_j^-1 y_j on the two lanes of row j: row h of the inverse
+      // times both components (the partner lane holds the other one)
+      const T yo = pair_swap(y);
+      if (l == j) y = xp * (h ? yo : y) + xq * (h ? y : yo);
+      if ((cm >> j) & 1u) {
+        const T xj0 = lane_bcast(y, 2 * j), xj1 = lane_bcast(y, 2 * j + 1);
+        if (l < j) y -= xp * xj0 + xq * xj1;
+      }
     }
   }
   if (l < t) c.y[sP<S>(tb + l, s) + h] = y;
@@ -1244,7 +1256,10 @@ __device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const D
   if (t == 0) return;
   const int l = ln >> 1, h = ln & 1;
   TailRow<T> R = TailRow<T>{};
-  for (int jb = 0; jb < t; jb += 8) {
+  constexpr int C = tail_cap<T>();
+#pragma unroll
+  for (int jb = 0; jb < C; jb += 8) {
+    if (jb >= t) break;
     int p[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -1261,8 +1276,7 @@ __device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const D
       if (b) { x0[u] = b[h]; x1[u] = b[2 + h]; }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (jb + u < t) { R.p[jb + u] = x0[u]; R.q[jb + u] = x1[u]; }
+    for (int u = 0; u < 8; ++u) { R.p[jb + u] = x0[u]; R.q[jb + u] = x1[u]; }
   }
   T y = T(0);
   if (l < t) {
@@ -1276,20 +1290,23 @@ __device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const D
   }
   const unsigned lm = __builtin_amdgcn_readfirstlane(m.tail_mask[t]);
   const unsigned cm = __builtin_amdgcn_readfirstlane(m.tail_mask[t + 1]);
-  for (int j = 0; j < t; ++j) {   // U^T w = g
-    const T xp = R.p[j], xq = R.q[j];
-    const T yo = pair_swap(y);
-    if (l == j) y = xp * (h ? yo : y) + xq * (h ? y : yo);
-    if ((lm >> j) & 1u) {
-      const T w0 = lane_bcast(y, 2 * j), w1 = lane_bcast(y, 2 * j + 1);
-      if (l > j && l < t) y -= xp * w0 + xq * w1;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {   // U^T w = g
+    if (j < t) {
+      const T xp = R.p[j], xq = R.q[j];
+      const T yo = pair_swap(y);
+      if (l == j) y = xp * (h ? yo : y) + xq * (h ? y : yo);
+      if ((lm >> j) & 1u) {
+        const T w0 = lane_bcast(y, 2 * j), w1 = lane_bcast(y, 2 * j + 1);
+        if (l > j && l < t) y -= xp * w0 + xq * w1;
+      }
     }
   }
-  for (int j = t - 1; j >= 0; --j) {   // L^T lambda = w
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {   // L^T lambda = w
     if ((cm >> j) & 1u) {
-      const T xp = R.p[j], xq = R.q[j];
       const T z0 = lane_bcast(y, 2 * j), z1 = lane_bcast(y, 2 * j + 1);
-      if (l < j) y -= xp * z0 + xq * z1;
+      if (l < j) y -= R.p[j] * z0 + R.q[j] * z1;
     }
   }
   if (l < t) c.y[sP<S>(tb + l, s) + h] = y;
