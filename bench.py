@@ -129,6 +129,7 @@ def main():
     import torch
     from gen.grids import SPECS, make_case
     from paper_2606_07099_amd import PFTemplate, PFLayer
+    from paper_2606_07099_amd.training import SyntheticDispatchTask
 
     name = args.workload
     spec, net, sc = make_case(name, scenario_mode=args.scenarios)
@@ -147,6 +148,10 @@ def main():
     tplr0 = PFTemplate.from_network(net, B, tol=spec.tol, precision="mixed", keep_factors=False,
                                     refine_steps=0)
     layer = PFLayer(tpllay)
+    # synthetic end-to-end training: an MLP proposes the decision block, the
+    # layer completes it (both steps), Adam updates the MLP
+    task = SyntheticDispatchTask(net, sc, dev, precision="mixed", tol=spec.tol)
+    train_losses = []
     # both completion steps (Step 2 recovers the generation block) under a
     # loss that adds a generation cost and a reactive-reserve penalty
     layerc = PFLayer(tpllay, recover=True)
@@ -192,13 +197,14 @@ def main():
         tplr0.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=outr0)
         layer_step()
         layer_completed_step()
+        train_losses.append(task.step())
     torch.cuda.synchronize()
 
     marks = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        e = [ev() for _ in range(7)]
+        e = [ev() for _ in range(8)]
         e[0].record(stream)
         tpl64.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=out64)
         e[1].record(stream)
@@ -212,6 +218,8 @@ def main():
         e[5].record(stream)
         layer_completed_step()
         e[6].record(stream)
+        train_losses.append(task.step())
+        e[7].record(stream)
         marks.append(e)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -222,6 +230,8 @@ def main():
     tad = np.array([m[3].elapsed_time(m[4]) for m in marks]) * 1e-3
     tr0 = np.array([m[4].elapsed_time(m[5]) for m in marks]) * 1e-3
     tfc = np.array([m[5].elapsed_time(m[6]) for m in marks]) * 1e-3
+    ttr = np.array([m[6].elapsed_time(m[7]) for m in marks]) * 1e-3
+    train_losses = [float(x) for x in train_losses]
     itad, stad, fnad = (x.cpu().numpy() for x in outad[2:])
     itr0, str0, fnr0 = (x.cpu().numpy() for x in outr0[2:])
     it64, st64, fn64 = (x.cpu().numpy() for x in out64[2:])
@@ -255,9 +265,18 @@ def main():
         "mixed_adaptive_solves_per_s": B / tad.mean(),
         "mixed_unrefined_solves_per_s": B / tr0.mean(),
         "layer_completed_fwd_bwd_samples_per_s": B / tfc.mean(),
+        "train_samples_per_s": B / ttr.mean(),
+        "train": {"task": "MLP (2 x 256 hidden) -> PV dispatch and |V| setpoints -> PF layer (both "
+                          "completion steps, mixed precision) -> generation cost + voltage and "
+                          "reactive penalties -> Adam",
+                  "loss_first": train_losses[0], "loss_last": train_losses[-1],
+                  "optimizer_steps": len(train_losses),
+                  "peak_torch_bytes": int(torch.cuda.max_memory_allocated()),
+                  "template_workspace_bytes": int(task.tpl.info()["workspace_bytes"])},
         "ms": {"fp64_solve": 1e3 * t64.mean(), "mixed_solve": 1e3 * tmp.mean(),
                "mixed_adaptive_solve": 1e3 * tad.mean(), "mixed_unrefined_solve": 1e3 * tr0.mean(),
                "layer_fwd_bwd": 1e3 * tfb.mean(), "layer_completed_fwd_bwd": 1e3 * tfc.mean(),
+               "train_step": 1e3 * ttr.mean(),
                "template_build": 1e3 * t_build},
         "iterations": {"fp64": np.bincount(it64).tolist(), "mixed": np.bincount(itmp).tolist(),
                        "mixed_adaptive": np.bincount(itad).tolist(),

@@ -1140,7 +1140,10 @@ __global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
     }
     __syncthreads();
     if (tid < S && s_st[tid] == 0 && piv[tid]) s_st[tid] = 3;
-    if (RES || S > 1) {   // scatter the slice into the per-scenario workspace
+    // LDS-resident slices: the kept state and factors go to the per-scenario
+    // workspace, which the adjoint copies into its own LDS slices; the
+    // HBM-resident adjoint reads this slice workspace in place
+    if (RES) {
       for (int s = 0; s < S; ++s) {
         const int b = slice * S + s;
         if (b >= kp.count) break;
