@@ -39,8 +39,8 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # Sources: profiles/k_newton_118bus_b1024_hbm_counters.md,
 # profiles/k_newton_1354bus_b4096_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "7d0c427523c47a4290b4b5a306514474e14632319026362bcc8fe7e9184ba928": {"c1": 6670899,
-                                                                         "c2": 46669982461},
+    "df14694171f3772cff5614304863ab7575942fa04730b95d0e8eecd611e8feef": {"c1": 7071417,
+                                                                         "c2": 46871671897},
 }
 
 
