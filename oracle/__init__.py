@@ -16,6 +16,8 @@ Contents (plain, slow, dense; every function cites the passage it follows):
 * :mod:`oracle.completion` -- Step-2 explicit recovery of the generation
   outputs and the gradients of the whole two-step completion (vbar2 through
   a dense J2, then the Step-1 transposed solve).
+* :mod:`oracle.operators` -- the base Jacobian template dF/dy with its
+  selector blocks and the operators J1, J1^T, J2^T, J3^T as dense sub-blocks.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against closed forms,
 invariants, finite differences, the paper's printed Jacobian entries
