@@ -251,6 +251,61 @@ int pf_adjoint_completed_batch(pf_template* tpl, const double* g_vm, const doubl
                                double* g_qd, double* g_pg, double* g_vset, void* hip_stream);
 
 /*
+ * The base Jacobian template and the operators the layer uses, as sparse
+ * matrices for interop (eq. J_base_block; step1_jacobian, Jstep2_impl and
+ * Jstep3_impl; block-aware indexing of Sec. III-B).  Orderings, each block
+ * ascending by bus: y = (p_g on B\D, q_g on B\D, |V| of every bus, theta of
+ * every bus), F = (dP of every bus, dQ of every bus).
+ *   PF_OP_BASE: J = dF/dy, 2 n_bus x (2 n_gen + 2 n_bus), n_gen = |B\D|;
+ *               dP_i/dp_g,i = dQ_i/dq_g,i = 1 (selectors), voltage blocks on
+ *               the Y_bus pattern (diagonal always present)
+ *   PF_OP_J1:   J1 = dF1/dz1, rows (dP on B\R, dQ on D), columns
+ *               (|V| on D, theta on B\R)
+ *   PF_OP_J1T:  J1^T
+ *   PF_OP_J2T:  J2^T, J2 = dF2/d(|V|, theta): rows (dP on R, dQ on B\D),
+ *               columns (|V| of every bus, theta of every bus)
+ *   PF_OP_J3T:  J3^T, J3 = dF1/d|V| on B\D
+ * One scenario's pattern is built once; the batch-global operator is the
+ * block-diagonal embedding of that pattern (eq. BDE_global: scenario b's block
+ * at row offset b*n_rows and column offset b*n_cols), whose CSR value array is
+ * exactly values[count][nnz] below.
+ */
+#define PF_OP_BASE 0
+#define PF_OP_J1 1
+#define PF_OP_J1T 2
+#define PF_OP_J2T 3
+#define PF_OP_J3T 4
+
+/*
+ * CSR pattern of operator `which` for one scenario, from the network alone
+ * (host; no device needed).  Host inputs as for pf_template_build (Y_bus rows
+ * need not be sorted).  Always writes *n_rows, *n_cols, *nnz and *nnz_base
+ * (non-zeros of the base J) when non-NULL; writes indptr[n_rows + 1],
+ * indices[nnz] (columns sorted within a row) and pos[nnz_base] (for each
+ * base entry, in the base's value order, its position in this operator's
+ * value array, or -1 if the operator does not use it: the position map of
+ * Algorithm 2) when those pointers are non-NULL, so a first call with NULL
+ * arrays queries the sizes.  Errors: PF_EINVAL.
+ */
+int pf_operator_pattern(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
+                        const int32_t* y_indices, int32_t which, int32_t* n_rows, int32_t* n_cols,
+                        int32_t* nnz, int32_t* nnz_base, int32_t* indptr, int32_t* indices,
+                        int32_t* pos);
+
+/*
+ * Values of operator `which` for scenarios [0, count) at the states
+ * (vm, va) (device [count][n_bus], FP64): device output values[count][nnz],
+ * in the order of pf_operator_pattern's CSR, evaluated in FP64 (Algorithm 1's
+ * entry formulas; selectors are 1).  count may exceed the template's batch:
+ * only the template's pattern is used, not its workspace.  The first call on
+ * a template allocates its small operator tables (device memory, released by
+ * pf_template_destroy); later calls allocate nothing.  Asynchronous on
+ * hip_stream.  Errors: PF_EINVAL, PF_ENOMEM, PF_EHIP.
+ */
+int pf_operator_values(pf_template* tpl, int32_t which, int32_t count, const double* vm,
+                       const double* va, double* values, void* hip_stream);
+
+/*
  * Evaluation entry points at a GIVEN state (vm, va device [batch][n_bus]),
  * for kernel-level checks and interop, in the paper's ordering: rows
  * (dP on B\R ascending bus, then dQ on D ascending bus), unknowns

@@ -16,10 +16,12 @@ PF_BUS_PQ, PF_BUS_PV, PF_BUS_SLACK = 0, 1, 2
 PF_FP64, PF_MIXED = 0, 1
 PF_STATUS_CONVERGED, PF_STATUS_MAX_ITER, PF_STATUS_NON_FINITE, PF_STATUS_ZERO_PIVOT = 0, 1, 2, 3
 PF_EVAL_MISMATCH, PF_EVAL_JACOBIAN, PF_EVAL_STEP, PF_EVAL_ADJOINT = 0, 1, 2, 3
+PF_OP_BASE, PF_OP_J1, PF_OP_J1T, PF_OP_J2T, PF_OP_J3T = 0, 1, 2, 3, 4
 
 EXPORTED = ("pf_default_options", "pf_last_error", "pf_ybus_from_branches", "pf_template_build",
             "pf_template_info", "pf_template_destroy", "pf_symbolic_analyze", "pf_solve_batch",
-            "pf_adjoint_batch", "pf_eval_batch", "pf_recover_batch", "pf_adjoint_completed_batch")
+            "pf_adjoint_batch", "pf_eval_batch", "pf_recover_batch", "pf_adjoint_completed_batch",
+            "pf_operator_pattern", "pf_operator_values")
 
 
 class PFOptions(ctypes.Structure):
@@ -83,7 +85,8 @@ def lib():
     L.pf_eval_batch.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     for name in ("pf_ybus_from_branches", "pf_template_build", "pf_template_info",
                  "pf_template_destroy", "pf_symbolic_analyze", "pf_solve_batch",
-                 "pf_adjoint_batch", "pf_eval_batch", "pf_recover_batch", "pf_adjoint_completed_batch"):
+                 "pf_adjoint_batch", "pf_eval_batch", "pf_recover_batch", "pf_adjoint_completed_batch",
+            "pf_operator_pattern", "pf_operator_values"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

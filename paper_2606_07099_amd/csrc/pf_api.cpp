@@ -12,7 +12,9 @@
 #include <string>
 #include <vector>
 
+#include "operators.h"
 #include "pf_kernels.h"
+#include "pf_operators.h"
 #include "sable_pf.h"
 #include "symbolic.h"
 
@@ -44,6 +46,12 @@ struct pf_template {
   void* wsl_t = nullptr;
   size_t ws_bytes = 0;
   bool have_factors = false;
+  // operator export tables, built on first use: the base entries (int4
+  // each), then the source map of every operator
+  void* d_ops = nullptr;
+  int32_t op_nbase = 0;
+  int32_t op_off[sable::OP_COUNT] = {};
+  int32_t op_nnz[sable::OP_COUNT] = {};
 };
 
 namespace {
@@ -502,6 +510,7 @@ int pf_template_destroy(pf_template* t) {
   if (t->ws_i) (void)hipFree(t->ws_i);
   if (t->wsl_d) (void)hipFree(t->wsl_d);
   if (t->wsl_t) (void)hipFree(t->wsl_t);
+  if (t->d_ops) (void)hipFree(t->d_ops);
   delete t;
   return PF_OK;
 }
@@ -597,6 +606,86 @@ int pf_eval_batch(pf_template* t, int32_t mode, int32_t count, const double* pd,
       return fail(PF_EINVAL, "pf_eval_batch: unknown mode");
   }
   if (he != hipSuccess) return hip_fail(he, "pf_eval_batch: launch");
+  return PF_OK;
+}
+
+int pf_operator_pattern(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
+                        const int32_t* y_indices, int32_t which, int32_t* n_rows, int32_t* n_cols,
+                        int32_t* nnz, int32_t* nnz_base, int32_t* indptr, int32_t* indices, int32_t* pos) {
+  g_err.clear();
+  if (n_bus < 2 || !bus_type || !y_indptr || !y_indices)
+    return fail(PF_EINVAL, "pf_operator_pattern: bad network arrays");
+  if (which < 0 || which >= sable::OP_COUNT) return fail(PF_EINVAL, "pf_operator_pattern: unknown operator");
+  const int32_t nnzY = y_indptr[n_bus];
+  if (y_indptr[0] != 0 || nnzY < 0) return fail(PF_EINVAL, "pf_operator_pattern: bad y_indptr");
+  for (int32_t i = 0; i < n_bus; ++i)
+    if (y_indptr[i + 1] < y_indptr[i]) return fail(PF_EINVAL, "pf_operator_pattern: bad y_indptr");
+  // the template stores Y_bus with each row's columns sorted; do the same
+  std::vector<int32_t> ci(y_indices, y_indices + nnzY);
+  for (int32_t i = 0; i < n_bus; ++i) std::sort(ci.begin() + y_indptr[i], ci.begin() + y_indptr[i + 1]);
+  sable::OperatorSet ops;
+  std::string err;
+  const int rc = sable::build_operators(n_bus, bus_type, y_indptr, ci.data(), ops, err);
+  if (rc != PF_OK) return fail(rc, "pf_operator_pattern: " + err);
+  const sable::OperatorPattern& op = ops.op[which];
+  if (n_rows) *n_rows = op.rows;
+  if (n_cols) *n_cols = op.cols;
+  if (nnz) *nnz = (int32_t)op.indices.size();
+  if (nnz_base) *nnz_base = (int32_t)ops.base.size();
+  if (indptr) std::copy(op.indptr.begin(), op.indptr.end(), indptr);
+  if (indices) std::copy(op.indices.begin(), op.indices.end(), indices);
+  if (pos) std::copy(op.pos.begin(), op.pos.end(), pos);
+  return PF_OK;
+}
+
+int pf_operator_values(pf_template* t, int32_t which, int32_t count, const double* vm, const double* va,
+                       double* values, void* hip_stream) {
+  g_err.clear();
+  if (!t) return fail(PF_EINVAL, "pf_operator_values: template is NULL");
+  if (which < 0 || which >= sable::OP_COUNT) return fail(PF_EINVAL, "pf_operator_values: unknown operator");
+  if (count < 0) return fail(PF_EINVAL, "pf_operator_values: negative count");
+  if (count > 0 && (!vm || !va || !values)) return fail(PF_EINVAL, "pf_operator_values: NULL array");
+  DeviceGuard g(t->device);
+  if (!t->d_ops) {
+    const sable::Symbolic& S = t->sym;
+    sable::OperatorSet ops;
+    std::string err;
+    const int rc = sable::build_operators(S.n_bus, S.bus_type.data(), S.y_rp.data(), S.y_ci.data(), ops, err);
+    if (rc != PF_OK) return fail(rc, "pf_operator_values: " + err);
+    std::vector<int32_t> buf;
+    for (const sable::BaseEntry& e : ops.base) buf.insert(buf.end(), {e.kind, e.i, e.j, e.q});
+    t->op_nbase = (int32_t)ops.base.size();
+    for (int k = 0; k < sable::OP_COUNT; ++k) {
+      t->op_off[k] = (int32_t)buf.size();
+      t->op_nnz[k] = (int32_t)ops.op[k].src.size();
+      buf.insert(buf.end(), ops.op[k].src.begin(), ops.op[k].src.end());
+    }
+    void* d = nullptr;
+    hipError_t he = hipMalloc(&d, buf.size() * sizeof(int32_t));
+    if (he != hipSuccess) return fail(PF_ENOMEM, "pf_operator_values: device allocation (operator tables)");
+    he = hipMemcpy(d, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+      (void)hipFree(d);
+      return hip_fail(he, "pf_operator_values: copy");
+    }
+    t->d_ops = d;
+  }
+  const unsigned char* img = static_cast<const unsigned char*>(t->d_sym);
+  sable::OpParams p{};
+  p.base = static_cast<const int4*>(t->d_ops);
+  p.src = static_cast<const int*>(t->d_ops) + t->op_off[which];
+  p.y_rp = reinterpret_cast<const int*>(img + t->so.y_rp);
+  p.y_ci = reinterpret_cast<const int*>(img + t->so.y_ci);
+  p.y_g = reinterpret_cast<const double*>(img + t->so.y_g);
+  p.y_b = reinterpret_cast<const double*>(img + t->so.y_b);
+  p.vm = vm;
+  p.va = va;
+  p.values = values;
+  p.nnz = t->op_nnz[which];
+  p.n_bus = t->sym.n_bus;
+  p.count = count;
+  hipError_t he = sable::launch_operator_values(p, static_cast<hipStream_t>(hip_stream));
+  if (he != hipSuccess) return hip_fail(he, "pf_operator_values: launch");
   return PF_OK;
 }
 

@@ -12,7 +12,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (PFError, PFOptions, PFStats, check, lib, PF_FP64, PF_MIXED, PF_EVAL_ADJOINT,
-                   PF_EVAL_JACOBIAN, PF_EVAL_MISMATCH, PF_EVAL_STEP)
+                   PF_EVAL_JACOBIAN, PF_EVAL_MISMATCH, PF_EVAL_STEP, PF_OP_BASE, PF_OP_J1, PF_OP_J1T,
+                   PF_OP_J2T, PF_OP_J3T)
 
 _I32P = ctypes.POINTER(ctypes.c_int32)
 _F64P = ctypes.POINTER(ctypes.c_double)
@@ -60,6 +61,27 @@ def symbolic_analyze(n_bus, bus_type, indptr, indices):
     order = np.zeros(n_bus - 1, np.int32)
     check(L.pf_symbolic_analyze(n_bus, btp, ipp, ixp, ctypes.byref(st), order.ctypes.data_as(_I32P)))
     return st.as_dict(), order
+
+
+def operator_pattern(n_bus, bus_type, indptr, indices, which):
+    """One scenario's CSR pattern of operator ``which`` (PF_OP_*), host only:
+    dict with n_rows, n_cols, indptr, indices and pos (the base-to-operator
+    position map, -1 where unused)."""
+    L = lib()
+    bt, btp = _i32(bus_type)
+    ip, ipp = _i32(indptr)
+    ix, ixp = _i32(indices)
+    nr, nc, nz, nzb = (ctypes.c_int32(0) for _ in range(4))
+    null = ctypes.cast(None, _I32P)
+    check(L.pf_operator_pattern(int(n_bus), btp, ipp, ixp, int(which), ctypes.byref(nr), ctypes.byref(nc),
+                                ctypes.byref(nz), ctypes.byref(nzb), null, null, null))
+    out_ptr = np.zeros(nr.value + 1, np.int32)
+    out_ix = np.zeros(nz.value, np.int32)
+    out_pos = np.zeros(nzb.value, np.int32)
+    check(L.pf_operator_pattern(int(n_bus), btp, ipp, ixp, int(which), ctypes.byref(nr), ctypes.byref(nc),
+                                ctypes.byref(nz), ctypes.byref(nzb), out_ptr.ctypes.data_as(_I32P),
+                                out_ix.ctypes.data_as(_I32P), out_pos.ctypes.data_as(_I32P)))
+    return {"n_rows": nr.value, "n_cols": nc.value, "indptr": out_ptr, "indices": out_ix, "pos": out_pos}
 
 
 def _stream_ptr(stream):
@@ -193,6 +215,47 @@ class PFTemplate:
                                                _stream_ptr(stream)))
         return tuple(outs)
 
+    def operator_pattern(self, which):
+        """One scenario's CSR pattern of operator ``which`` (see :func:`operator_pattern`)."""
+        return operator_pattern(self.n_bus, self._bt, self._ip, self._ix, which)
+
+    def operator(self, which, vm, va, *, out=None, stream=None):
+        """Batch-global operator ``which`` at the states (vm, va) [count, n_bus]:
+        a torch sparse CSR tensor that embeds each scenario's block on the
+        diagonal (eq. BDE_global).  Its pattern is built once per (operator,
+        count) and cached; pass a previous result as ``out`` to refresh its
+        value array in place instead of allocating a new one."""
+        import torch
+        count = int(vm.shape[0])
+        if vm.dtype != torch.float64 or not vm.is_contiguous() or tuple(vm.shape) != (count, self.n_bus):
+            raise ValueError("vm must be contiguous float64 [count, n_bus]")
+        if va.dtype != torch.float64 or not va.is_contiguous() or tuple(va.shape) != (count, self.n_bus):
+            raise ValueError("va must be contiguous float64 [count, n_bus]")
+        cache = self.__dict__.setdefault("_op_cache", {})
+        key = (int(which), count, vm.device)
+        if key not in cache:
+            pat = self.operator_pattern(which)
+            nr, nc, nnz = pat["n_rows"], pat["n_cols"], int(pat["indices"].size)
+            ip = torch.as_tensor(pat["indptr"], dtype=torch.int64)
+            ix = torch.as_tensor(pat["indices"], dtype=torch.int64)
+            crow = torch.cat([(ip[:-1].unsqueeze(0) + nnz * torch.arange(count).unsqueeze(1)).reshape(-1),
+                              torch.tensor([nnz * count])]).to(vm.device)
+            col = (ix.unsqueeze(0) + nc * torch.arange(count).unsqueeze(1)).reshape(-1).to(vm.device)
+            cache[key] = (crow, col, nnz, (count * nr, count * nc))
+        crow, col, nnz, shape = cache[key]
+        if out is not None:
+            values = out.values()
+            if values.numel() != count * nnz or not values.is_contiguous():
+                raise ValueError("out does not match this operator and batch")
+        else:
+            values = torch.empty(count * nnz, dtype=torch.float64, device=vm.device)
+        check(lib().pf_operator_values(self._h, int(which), count, ctypes.c_void_p(vm.data_ptr()),
+                                       ctypes.c_void_p(va.data_ptr()), ctypes.c_void_p(values.data_ptr()),
+                                       _stream_ptr(stream)))
+        if out is not None:
+            return out
+        return torch.sparse_csr_tensor(crow, col, values, size=shape)
+
     def evaluate(self, mode, pd, qd, pg, vset, vm, va, rhs=None, count=None, *, stream=None):
         """Kernel-level evaluation at a given state (see ``pf_eval_batch``)."""
         import torch
@@ -214,5 +277,6 @@ class PFTemplate:
         return out
 
 
-__all__ = ["PFTemplate", "ybus_from_branches", "symbolic_analyze", "PFError", "PF_EVAL_MISMATCH",
-           "PF_EVAL_JACOBIAN", "PF_EVAL_STEP", "PF_EVAL_ADJOINT"]
+__all__ = ["PFTemplate", "ybus_from_branches", "symbolic_analyze", "operator_pattern", "PFError",
+           "PF_EVAL_MISMATCH", "PF_EVAL_JACOBIAN", "PF_EVAL_STEP", "PF_EVAL_ADJOINT", "PF_OP_BASE",
+           "PF_OP_J1", "PF_OP_J1T", "PF_OP_J2T", "PF_OP_J3T"]
