@@ -298,9 +298,13 @@ int pf_operator_pattern(int32_t n_bus, const int32_t* bus_type, const int32_t* y
  * in the order of pf_operator_pattern's CSR, evaluated in FP64 (Algorithm 1's
  * entry formulas; selectors are 1).  count may exceed the template's batch:
  * only the template's pattern is used, not its workspace.  The first call on
- * a template allocates its small operator tables (device memory, released by
- * pf_template_destroy); later calls allocate nothing.  Asynchronous on
- * hip_stream.  Errors: PF_EINVAL, PF_ENOMEM, PF_EHIP.
+ * a template allocates its small operator tables and a buffer of
+ * 32 * count * n_bus bytes for the per-bus voltages and injections (device memory,
+ * released by pf_template_destroy); a later call with a larger count grows
+ * that buffer (after a device synchronisation), any other call allocates
+ * nothing.  Calls on one template share the buffer: calls that overlap on
+ * different streams race.  Asynchronous on hip_stream.  Errors: PF_EINVAL,
+ * PF_ENOMEM, PF_EHIP.
  */
 int pf_operator_values(pf_template* tpl, int32_t which, int32_t count, const double* vm,
                        const double* va, double* values, void* hip_stream);

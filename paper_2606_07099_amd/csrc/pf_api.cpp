@@ -52,6 +52,8 @@ struct pf_template {
   int32_t op_nbase = 0;
   int32_t op_off[sable::OP_COUNT] = {};
   int32_t op_nnz[sable::OP_COUNT] = {};
+  double* d_opef = nullptr;   // per-bus state (e, f, P, Q) of the last operator refresh
+  size_t opef_count = 0;      // scenarios it holds
 };
 
 namespace {
@@ -511,6 +513,7 @@ int pf_template_destroy(pf_template* t) {
   if (t->wsl_d) (void)hipFree(t->wsl_d);
   if (t->wsl_t) (void)hipFree(t->wsl_t);
   if (t->d_ops) (void)hipFree(t->d_ops);
+  if (t->d_opef) (void)hipFree(t->d_opef);
   delete t;
   return PF_OK;
 }
@@ -670,6 +673,18 @@ int pf_operator_values(pf_template* t, int32_t which, int32_t count, const doubl
     }
     t->d_ops = d;
   }
+  if ((size_t)count > t->opef_count) {   // grow the state buffer (previous work may still read it)
+    (void)hipDeviceSynchronize();
+    if (t->d_opef) (void)hipFree(t->d_opef);
+    t->d_opef = nullptr;
+    t->opef_count = 0;
+    hipError_t he = hipMalloc(&t->d_opef, (size_t)count * t->sym.n_bus * 4 * sizeof(double));
+    if (he != hipSuccess) {
+      t->d_opef = nullptr;
+      return fail(PF_ENOMEM, "pf_operator_values: device allocation (per-bus state)");
+    }
+    t->opef_count = (size_t)count;
+  }
   const unsigned char* img = static_cast<const unsigned char*>(t->d_sym);
   sable::OpParams p{};
   p.base = static_cast<const int4*>(t->d_ops);
@@ -680,6 +695,7 @@ int pf_operator_values(pf_template* t, int32_t which, int32_t count, const doubl
   p.y_b = reinterpret_cast<const double*>(img + t->so.y_b);
   p.vm = vm;
   p.va = va;
+  p.ef = t->d_opef;
   p.values = values;
   p.nnz = t->op_nnz[which];
   p.n_bus = t->sym.n_bus;

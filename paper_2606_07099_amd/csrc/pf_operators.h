@@ -12,10 +12,12 @@ struct OpParams {
   const int *y_rp, *y_ci;
   const double *y_g, *y_b;
   const double *vm, *va; // [count][n_bus] state of each scenario
+  double* ef;            // [count][n_bus] (e, f, P, Q): e + jf = V, P + jQ = V conj(I), formed first
   double* values;        // [count][nnz]: the value array of the batch-global (block-diagonal) CSR
   int nnz, n_bus, count;
 };
 
+// two launches on st: the per-bus state, then the values
 hipError_t launch_operator_values(const OpParams& p, hipStream_t st);
 
 }  // namespace sable
