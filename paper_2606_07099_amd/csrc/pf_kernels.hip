@@ -713,7 +713,12 @@ __device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c,
   T y = T(0);   // component h of the right-hand side of row l
   if (fwd && l < t) y = c.y[sP<S>(tb + l, s) + h];
   bool zero = false;
+  // the structure mask of the next pivot is loaded one pivot ahead, so its
+  // LDS latency hides behind the current pivot's work
+  unsigned mnext = m.tail_mask[0];
   for (int k = 0; k < t; ++k) {
+    const unsigned mk = __builtin_amdgcn_readfirstlane(mnext);   // U columns j > k
+    if (k + 1 < t) mnext = m.tail_mask[k + 1];
     const T xp = R.p[k], xq = R.q[k];
     const T da = lane_bcast(xp, 2 * k), db = lane_bcast(xq, 2 * k);
     const T dc = lane_bcast(xp, 2 * k + 1), dd = lane_bcast(xq, 2 * k + 1);
@@ -722,8 +727,8 @@ __device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c,
     const T ia = dd * inv, ib = -db * inv, ic = -dc * inv, id = da * inv;
     // pivots of the block: a, then the Schur complement d - c b / a
     const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
-    zero |= !(fabs(da) > eps * (fabs(da) + fabs(db))) ||
-            !(fabs(det) > eps * fabs(da) * (fabs(dc) + fabs(dd))) || !isfinite(inv);
+    zero |= !(fabs(da) > eps * (fabs(da) + fabs(db))) |
+            !(fabs(det) > eps * fabs(da) * (fabs(dc) + fabs(dd))) | !isfinite(inv);
     const bool below = l > k && l < t;
     // row h of A_lk D_k^-1 on the rows below the pivot, zero elsewhere, so
     // that the update below needs no per-lane select
@@ -734,14 +739,19 @@ __device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c,
       const T yk0 = lane_bcast(y, 2 * k), yk1 = lane_bcast(y, 2 * k + 1);
       y -= l0 * yk0 + l1 * yk1;
     }
-    const unsigned mk = __builtin_amdgcn_readfirstlane(m.tail_mask[k]);   // U columns j > k
+    // eight columns per uniform test, then one test per column
 #pragma unroll
-    for (int j = 0; j < tail_cap<T>(); ++j) {
-      if ((mk >> j) & 1u) {
-        const T ua = lane_bcast(R.p[j], 2 * k), ub = lane_bcast(R.q[j], 2 * k);
-        const T uc = lane_bcast(R.p[j], 2 * k + 1), ud = lane_bcast(R.q[j], 2 * k + 1);
-        R.p[j] -= l0 * ua + l1 * uc;
-        R.q[j] -= l0 * ub + l1 * ud;
+    for (int jb = 0; jb < tail_cap<T>(); jb += 8) {
+      if ((mk >> jb) & 0xFFu) {
+#pragma unroll
+        for (int j = jb; j < jb + 8; ++j) {
+          if ((mk >> j) & 1u) {
+            const T ua = lane_bcast(R.p[j], 2 * k), ub = lane_bcast(R.q[j], 2 * k);
+            const T uc = lane_bcast(R.p[j], 2 * k + 1), ud = lane_bcast(R.q[j], 2 * k + 1);
+            R.p[j] -= l0 * ua + l1 * uc;
+            R.q[j] -= l0 * ub + l1 * ud;
+          }
+        }
       }
     }
   }
