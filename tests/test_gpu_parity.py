@@ -252,3 +252,45 @@ def test_adjoint_requires_a_solve(device):
     tpl2.solve(d["pd"], d["qd"], d["pg"], d["vset"])
     with pytest.raises(PFError):
         tpl2.adjoint(g, g)
+
+
+@pytest.mark.parametrize("batch", [1, 3, 1023])
+def test_ragged_and_single_scenario_batches(batch, device):
+    """LDS-resident slices of 4 scenarios with a ragged last slice (and a
+    batch of one): every scenario still matches the oracle."""
+    import torch
+    spec, net, sc, tpl, d, tol = make_gpu_case("c1", device, batch=batch, precision="mixed")
+    assert tpl.info()["lds_resident"] == 1
+    res = tpl.solve(d["pd"], d["qd"], d["pg"], d["vset"])
+    torch.cuda.synchronize()
+    which = np.unique(np.array([0, batch // 2, batch - 1]))
+    oracle = newton_batch(ybus_of(net), net.bus_type, sc, tol=tol, which=which)
+    _check_solution(net, sc, which, res, oracle, tol, iters_slack=1)
+
+
+def test_zero_admittance_branch_gives_zero_pivot_status(device):
+    """A branch whose admittance entries are present in the pattern but zero
+    leaves its far bus with an all-zero Jacobian block: the factorisation
+    reports status 3 (zero pivot) for that scenario, and the dense oracle
+    Jacobian is exactly singular there."""
+    import torch
+    from paper_2606_07099_amd import PFTemplate
+    # slack 0 -- PQ 1 -- PQ 2, the 1-2 branch with zero admittance
+    y01 = 1.0 / complex(0.01, 0.1)
+    Yd = np.zeros((3, 3), complex)
+    Yd[0, 0] = Yd[1, 1] = y01
+    Yd[0, 1] = Yd[1, 0] = -y01
+    indptr = np.array([0, 2, 5, 7], np.int32)
+    indices = np.array([0, 1, 0, 1, 2, 1, 2], np.int32)
+    g = np.array([Yd[r, c].real for r, c in zip([0, 0, 1, 1, 1, 2, 2], indices)])
+    b = np.array([Yd[r, c].imag for r, c in zip([0, 0, 1, 1, 1, 2, 2], indices)])
+    bt = np.array([2, 0, 0], np.int32)
+    tpl = PFTemplate(3, bt, indptr, indices, g, b, 2, tol=1e-10)
+    pd = torch.tensor([[0.0, 0.3, 0.0], [0.0, 0.3, 0.2]], dtype=torch.float64, device=device)
+    qd = 0.1 * pd
+    vset = torch.ones_like(pd)
+    vm, va, iters, status, fn = (x.cpu().numpy() for x in tpl.solve(pd, qd, None, vset))
+    assert status[0] == 3 and status[1] == 3
+    from oracle.newton import Index, j1
+    J = j1(Yd, np.ones(3, complex), Index.of(bt))
+    assert np.linalg.matrix_rank(J) < J.shape[0]
