@@ -39,7 +39,33 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed")
     os.replace(tmp, LIB)
+    build_abi_check(verbose)
     return LIB
+
+
+ABI_CHECK = os.path.join(HERE, "abi_check")
+
+
+def build_abi_check(verbose: bool = False) -> str:
+    """The plain C client of the ABI (``csrc/abi_check.c``), linked against the
+    library next to it; the tests run it as a child process."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        raise RuntimeError("no C compiler found")
+    tmp = ABI_CHECK + ".tmp"
+    cmd = [cc, "-std=c11", "-O2", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
+           "-I", os.path.join(ROOT, "include"), os.path.join(CSRC, "abi_check.c"), "-o", tmp,
+           "-L", HERE, "-lsablepf", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("C client build failed")
+    os.replace(tmp, ABI_CHECK)
+    return ABI_CHECK
 
 
 if __name__ == "__main__":
