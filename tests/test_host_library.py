@@ -167,3 +167,22 @@ def test_ybus_rejects_self_loops_and_small_capacity(L):
                                  ix.ctypes.data_as(I32), gg.ctypes.data_as(F64), gg.ctypes.data_as(F64),
                                  2, ctypes.byref(nnz))
     assert rc != 0 and nnz.value == 7
+
+
+def test_template_build_rejects_empty_batches_and_bad_options(L):
+    """Argument checks that run before any device call: an empty batch, a
+    bad precision, too many refinement steps and a block size that is not a
+    multiple of the wavefront all fail with PF_EINVAL and a message."""
+    from paper_2606_07099_amd import PFTemplate
+    from paper_2606_07099_amd._lib import PFError, PF_EINVAL
+    from paper_2606_07099_amd.pf import ybus_from_branches
+    n, f, t = 3, np.array([0, 1]), np.array([1, 2])
+    ip, ix, g, b = ybus_from_branches(n, f, t, np.full(2, 0.01), np.full(2, 0.1), np.zeros(2))
+    bt = np.array([SLACK, PQ, PQ], np.int32)
+    for kw in ({"batch": 0}, {"batch": -3}, {"batch": 4, "refine_steps": 17},
+               {"batch": 4, "block_threads": 100}, {"batch": 4, "max_iter": -1}, {"batch": 4, "tol": 0.0}):
+        batch = kw.pop("batch")
+        with pytest.raises(PFError) as e:
+            PFTemplate(n, bt, ip, ix, g, b, batch, **kw)
+        assert e.value.code == PF_EINVAL
+        assert L.pf_last_error().decode()
