@@ -85,8 +85,8 @@ typedef struct {
   int32_t keep_factors;  /* 1 (default): after convergence re-evaluate J1 and refactor
                             at the solution and keep the factors for pf_adjoint_batch */
   int32_t block_threads; /* threads per workgroup, 0 = automatic (64..1024); LDS-resident
-                            slices always run 256 threads, so any other nonzero value
-                            selects HBM-resident slices */
+                            slices always run 512 threads (PF_MIXED) or 256 (PF_FP64),
+                            so any other nonzero value selects HBM-resident slices */
   int32_t refine_adaptive; /* PF_MIXED forward solve: 0 (default) applies all refine_steps
                             refinement solves; 1 computes the FP64 residual r of the
                             current correction and refines only while

@@ -408,7 +408,8 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   const size_t per_scen = 8 * (size_t)t->llay.sd + tsz * (size_t)t->llay.st;
   int best_s = 0;
   size_t best_score = 0;
-  const bool res_ok = opt.block_threads == 0 || opt.block_threads == sable::kResThreads;
+  const int res_nt = sable::res_newton_threads(t->fp32);
+  const bool res_ok = opt.block_threads == 0 || opt.block_threads == res_nt;
   for (int sl : {4, 2, 1}) {
     if (!res_ok || sl > sable::kResMaxSlice) continue;
     const size_t need = sable::kScratchBytes + (size_t)so.newton_bytes + sl * per_scen;
@@ -437,7 +438,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     t->lds_res = true;
     t->slice = best_s;
     t->lds_bytes = sable::kScratchBytes + (size_t)so.newton_bytes + best_s * per_scen;
-    nt = sable::kResThreads;
+    nt = res_nt;
   } else {
     // HBM-resident: S scenarios interleaved per slice, S as large as keeps
     // at least one slice per compute unit

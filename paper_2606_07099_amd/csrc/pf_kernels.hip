@@ -932,7 +932,7 @@ __device__ __forceinline__ void phase_set_state(const Dims& D, St<T>& c, int tid
 // the Newton kernel: one workgroup = one slice of S scenarios
 
 template <typename T, bool RES, int S>
-__global__ void __launch_bounds__(RES ? 256 : 1024) k_newton(KParams kp) {
+__global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton(KParams kp) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int slice = blockIdx.x;
@@ -1633,7 +1633,7 @@ template <typename T>
 static hipError_t launch_newton_t(const KParams& kp, int slice, int grid, int nt, size_t lds,
                                   bool res, hipStream_t st) {
   dim3 g(grid), b(nt);
-  if (res && (nt != kResThreads || slice > kResMaxSlice)) return hipErrorInvalidValue;
+  if (res && (nt != res_newton_threads<T>() || slice > kResMaxSlice)) return hipErrorInvalidValue;
   if (!res) {
     switch (slice) {
       case 1: hipLaunchKernelGGL((k_newton<T, false, 1>), g, b, lds, st, kp); break;
