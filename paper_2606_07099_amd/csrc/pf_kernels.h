@@ -101,8 +101,8 @@ struct KParams {
 // threads with FP32 factors (the extra wavefronts hide LDS latency in the
 // barrier-separated phases) and 256 with FP64 factors (whose register tail
 // needs more than the 256 registers a 512-thread workgroup leaves a
-// wavefront); the adjoint runs 256.
-constexpr int kResThreads = 256;
+// wavefront); the adjoint runs kResThreads.
+constexpr int kResThreads = 512;
 constexpr int kResMaxSlice = 4;
 template <typename T>
 constexpr int res_newton_threads() { return sizeof(T) == 4 ? 512 : 256; }
