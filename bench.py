@@ -39,8 +39,8 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # Sources: profiles/k_newton_118bus_b1024_hbm_counters.md,
 # profiles/k_newton_1354bus_b4096_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "3b60cb03117ec655183f75883c04660a1cdea73ea57649b5c3f7a375fb8c8ae1": {"c1": 7065275,
-                                                                         "c2": 46868490601},
+    "f4344e057ca13a64399583d6cb337d21c14498c2ef2be3e56b40ecd6fbce02be": {"c1": 7060150,
+                                                                         "c2": 46862670514},
 }
 
 
