@@ -307,6 +307,12 @@ def main():
                       "mixed_adaptive": int((stad == 0).sum()), "mixed_unrefined": int((str0 == 0).sum())},
         "max_final_mismatch": {"fp64": float(fn64.max()), "mixed": float(fnmp.max()),
                                "mixed_adaptive": float(fnad.max()), "mixed_unrefined": float(fnr0.max())},
+        "device_memory": {"templates_workspace_bytes": int(sum(t.info()["workspace_bytes"] for t in
+                                                              (tpl64, tplmp, tpllay, tplad, tplr0, task.tpl))),
+                          "torch_peak_bytes": int(torch.cuda.max_memory_allocated()),
+                          "per_template": {"fp64": int(info64["workspace_bytes"]),
+                                           "mixed": int(infomp["workspace_bytes"]),
+                                           "mixed_keep_factors": int(tpllay.info()["workspace_bytes"])}},
         "template": {k: infomp[k] for k in ("n_j", "nnz_j1", "nnzb_lu", "nnz_lu", "fill_ratio",
                                             "n_levels_l", "n_levels_u", "lds_resident",
                                             "block_threads", "lds_bytes", "slice_width", "workspace_bytes")},

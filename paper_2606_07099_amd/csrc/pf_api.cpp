@@ -194,8 +194,8 @@ sable::KParams base_params(const pf_template* t) {
   kp.lay = t->lay;
   kp.llay = t->llay;
   kp.alay = t->alay;
-  kp.ws_d = t->ws_d;
-  kp.ws_t = t->ws_t;
+  kp.ws_d = t->ws_d ? t->ws_d : t->wsl_d;   // wide HBM-resident slices: the slice workspace
+  kp.ws_t = t->ws_t ? t->ws_t : t->wsl_t;   // serves as per-scenario scratch
   kp.ws_i = t->ws_i;
   kp.wsl_d = t->wsl_d ? t->wsl_d : t->ws_d;
   kp.wsl_t = t->wsl_t ? t->wsl_t : t->ws_t;
@@ -461,10 +461,15 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   he = hipMemcpy(t->d_sym, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
   if (he != hipSuccess) { pf_template_destroy(t); return hip_fail(he, "pf_template_build: upload"); }
 
-  // ---- per-scenario workspace for the whole batch
-  const size_t bd = (size_t)batch * t->lay.sd * 8, bt = (size_t)batch * t->lay.st * tsz,
+  // ---- workspace.  LDS-resident slices and HBM-resident slices of one
+  // scenario use the per-scenario layout; wider HBM-resident slices use the
+  // slice workspace only (their adjoint reads it in place), and the dense
+  // Jacobian export borrows it as per-scenario scratch
+  const bool scen_ws = t->lds_res || t->slice == 1;
+  const size_t bd = scen_ws ? (size_t)batch * t->lay.sd * 8 : 0,
+               bt = scen_ws ? (size_t)batch * t->lay.st * tsz : 0,
                bi = (size_t)batch * 4 * sizeof(int);
-  if (hipMalloc(&t->ws_d, bd) != hipSuccess || hipMalloc(&t->ws_t, bt) != hipSuccess ||
+  if ((scen_ws && (hipMalloc(&t->ws_d, bd) != hipSuccess || hipMalloc(&t->ws_t, bt) != hipSuccess)) ||
       hipMalloc(&t->ws_i, bi) != hipSuccess) {
     pf_template_destroy(t);
     return fail(PF_ENOMEM, "pf_template_build: device allocation (workspace)");
