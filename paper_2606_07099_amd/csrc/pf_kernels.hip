@@ -201,10 +201,42 @@ __device__ __forceinline__ Grp groups(int nitems, int tid, int nt, int gmin) {
   return {G, tid >> lg, tid & (G - 1), nt >> lg};
 }
 
-// sum over the G/S entry lanes of one scenario inside a group
+// value of lane (this lane xor O): partners within a 16-lane row move by DPP
+// (a VALU operation: quad permutations for O = 1, 2; a row shift left or
+// right, picked per lane, for O = 4, 8), farther partners by ds_bpermute
+template <int O>
+__device__ __forceinline__ int xor_lane(int v) {
+  if constexpr (O == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  else if constexpr (O == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  else if constexpr (O == 4 || O == 8) {
+    const int up = __builtin_amdgcn_mov_dpp(v, 0x100 | O, 0xF, 0xF, false);     // row_shl: lane + O
+    const int down = __builtin_amdgcn_mov_dpp(v, 0x110 | O, 0xF, 0xF, false);   // row_shr: lane - O
+    return (__lane_id() & O) ? down : up;
+  } else {
+    return __shfl_xor(v, O);
+  }
+}
+template <int O>
+__device__ __forceinline__ float xor_lane(float v) {
+  return __int_as_float(xor_lane<O>(__float_as_int(v)));
+}
+template <int O>
+__device__ __forceinline__ double xor_lane(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = xor_lane<O>((int)(b & 0xffffffffll)), hi = xor_lane<O>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over the G/S entry lanes of one scenario inside a group (G a power of
+// two, groups aligned to G lanes, every lane of a group active)
 template <typename T, int S>
 __device__ __forceinline__ T group_sum(T v, int G) {
-  for (int o = G >> 1; o >= S; o >>= 1) v += __shfl_xor(v, o);
+  if (G > 32 && S <= 32) v += xor_lane<32>(v);
+  if (G > 16 && S <= 16) v += xor_lane<16>(v);
+  if (G > 8 && S <= 8) v += xor_lane<8>(v);
+  if (G > 4 && S <= 4) v += xor_lane<4>(v);
+  if (G > 2 && S <= 2) v += xor_lane<2>(v);
+  if (G > 1 && S <= 1) v += xor_lane<1>(v);
   return v;
 }
 
