@@ -246,10 +246,12 @@ template <int S>
 __device__ __forceinline__ void block_max(double v, int bad, unsigned char* scr, int tid, int nt) {
   double* red = reinterpret_cast<double*>(scr + kRedOff);
   int* flg = reinterpret_cast<int*>(scr + kFlagOff);
-  for (int o = 32; o >= S; o >>= 1) {
-    v = fmax(v, __shfl_xor(v, o));
-    bad |= __shfl_xor(bad, o);
-  }
+  if (S <= 32) { v = fmax(v, xor_lane<32>(v)); bad |= xor_lane<32>(bad); }
+  if (S <= 16) { v = fmax(v, xor_lane<16>(v)); bad |= xor_lane<16>(bad); }
+  if (S <= 8) { v = fmax(v, xor_lane<8>(v)); bad |= xor_lane<8>(bad); }
+  if (S <= 4) { v = fmax(v, xor_lane<4>(v)); bad |= xor_lane<4>(bad); }
+  if (S <= 2) { v = fmax(v, xor_lane<2>(v)); bad |= xor_lane<2>(bad); }
+  if (S <= 1) { v = fmax(v, xor_lane<1>(v)); bad |= xor_lane<1>(bad); }
   const int w = tid >> 6, l = tid & 63;
   if (l < S) { red[w * S + l] = v; flg[w * S + l] = bad; }
   __syncthreads();
