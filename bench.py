@@ -39,8 +39,8 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # Sources: profiles/k_newton_118bus_b1024_hbm_counters.md,
 # profiles/k_newton_1354bus_b4096_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "f4344e057ca13a64399583d6cb337d21c14498c2ef2be3e56b40ecd6fbce02be": {"c1": 7060150,
-                                                                         "c2": 46862670514},
+    "998f93fe6206dede667f622c864bafc12291a7feb16168658ea4f15600c1f12f": {"c1": 7079616,
+                                                                         "c2": 46864333251},
 }
 
 
