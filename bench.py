@@ -39,8 +39,8 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # Sources: profiles/k_newton_118bus_b1024_hbm_counters.md,
 # profiles/k_newton_1354bus_b4096_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "998f93fe6206dede667f622c864bafc12291a7feb16168658ea4f15600c1f12f": {"c1": 7079616,
-                                                                         "c2": 46864333251},
+    "44291393a6099d150ec4129d4d79efb6b8a8ca3ca9e1745f127a5ec1c54fce7e": {"c1": 7079600,
+                                                                         "c2": 46534616170},
 }
 
 

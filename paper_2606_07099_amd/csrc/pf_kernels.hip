@@ -33,6 +33,13 @@ template <typename T>
 __device__ __forceinline__ Blk<T> ld_blk(const T* p) { return {p[0], p[1], p[2], p[3]}; }
 template <typename T>
 __device__ __forceinline__ void st_blk(T* p, const Blk<T>& x) { p[0] = x.a; p[1] = x.b; p[2] = x.c; p[3] = x.d; }
+// streaming block load: HBM values read once per pass, marked non-temporal
+// so that they do not displace the gathered unknowns from the caches
+template <typename T>
+__device__ __forceinline__ Blk<T> ld_blk_nt(const T* p) {
+  return {__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1), __builtin_nontemporal_load(p + 2),
+          __builtin_nontemporal_load(p + 3)};
+}
 
 template <typename T>
 __device__ __forceinline__ Blk<T> mul(const Blk<T>& x, const Blk<T>& y) {
@@ -467,7 +474,7 @@ __device__ __forceinline__ void phase_solve(const Sym& m, const Dims& D, St<T>& 
       const int a = r.x, n = rw[ri + 1].w - r.w;
       T s0 = T(0), s1 = T(0);
       for (int j = e; j < n; j += E) {
-        const Blk<T> M = ld_blk(c.lu + sB<S>(r.y + j, s));
+        const Blk<T> M = RES ? ld_blk(c.lu + sB<S>(r.y + j, s)) : ld_blk_nt(c.lu + sB<S>(r.y + j, s));
         const int k = cols[r.w + j];
         const T z0 = c.y[sP<S>(k, s)], z1 = c.y[sP<S>(k, s) + 1];
         s0 += M.a * z0 + M.b * z1;
