@@ -1225,11 +1225,12 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
 __device__ __forceinline__ void gen_direct(const KParams& kp, size_t o, int bt, double& gpd, double& gqd,
                                            double& gpg) {
   if (kp.mode != MODE_SOLVE) return;
-  if (kp.g_pgo) {
-    if (bt == 2) gpd += kp.g_pgo[o];
-    if (bt == 1) gpg += kp.g_pgo[o];
-  }
-  if (kp.g_qgo && bt != 0) gqd += kp.g_qgo[o];
+  // value selects, so that the three sums stay in registers
+  const double gp = kp.g_pgo ? kp.g_pgo[o] : 0.0;
+  const double gq = (kp.g_qgo && bt != 0) ? kp.g_qgo[o] : 0.0;
+  gpd = (kp.g_pgo && bt == 2) ? gpd + gp : gpd;
+  gpg = (kp.g_pgo && bt == 1) ? gpg + gp : gpg;
+  gqd = (kp.g_qgo && bt != 0) ? gqd + gq : gqd;
 }
 
 // ----------------------------------------------------------------------------
