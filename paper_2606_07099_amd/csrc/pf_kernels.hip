@@ -753,7 +753,9 @@ __device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c,
   rt_load<T, S>(m, D, c, s, l, h, R);
   T y = T(0);   // component h of the right-hand side of row l
   if (fwd && l < t) y = c.y[sP<S>(tb + l, s) + h];
-  bool zero = false;
+  // this lane's row of its own pivot block as it was when eliminated, for
+  // the pivot test after the loop
+  T pvp = T(0), pvq = T(0);
   // the structure mask of the next pivot is loaded one pivot ahead, so its
   // LDS latency hides behind the current pivot's work
   unsigned mnext = m.tail_mask[0];
@@ -766,16 +768,19 @@ __device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c,
     const T det = da * dd - db * dc;
     const T inv = recip(det);
     const T ia = dd * inv, ib = -db * inv, ic = -dc * inv, id = da * inv;
-    // pivots of the block: a, then the Schur complement d - c b / a
-    const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
-    zero |= !(fabs(da) > eps * (fabs(da) + fabs(db))) |
-            !(fabs(det) > eps * fabs(da) * (fabs(dc) + fabs(dd))) | !isfinite(inv);
+    pvp = l == k ? xp : pvp;
+    pvq = l == k ? xq : pvq;
     const bool below = l > k && l < t;
     // row h of A_lk D_k^-1 on the rows below the pivot, zero elsewhere, so
-    // that the update below needs no per-lane select
-    const T l0 = below ? xp * ia + xq * ic : T(0), l1 = below ? xp * ib + xq * id : T(0);
-    R.p[k] = below ? l0 : (l == k ? (h ? ic : ia) : xp);
-    R.q[k] = below ? l1 : (l == k ? (h ? id : ib) : xq);
+    // that the update below needs no per-lane select; every lane forms the
+    // products and selects by value (no divergent branch around the
+    // register-indexed writes)
+    const T m0 = xp * ia + xq * ic, m1 = xp * ib + xq * id;
+    const T l0 = below ? m0 : T(0), l1 = below ? m1 : T(0);
+    const T np = below ? m0 : (l == k ? (h ? ic : ia) : xp);
+    const T nq = below ? m1 : (l == k ? (h ? id : ib) : xq);
+    R.p[k] = np;
+    R.q[k] = nq;
     if (fwd) {
       const T yk0 = lane_bcast(y, 2 * k), yk1 = lane_bcast(y, 2 * k + 1);
       y -= l0 * yk0 + l1 * yk1;
@@ -796,7 +801,19 @@ __device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c,
       }
     }
   }
-  if (zero && ln == 0) piv[s] = 1;
+  // the pivot test of every block at once (the same arithmetic as at its
+  // elimination): a, then the Schur complement d - c b / a, must stand out
+  // of the block's scale, and the inverse must be finite
+  {
+    const T op = pair_swap(pvp), oq = pair_swap(pvq);
+    const T da = h ? op : pvp, db = h ? oq : pvq, dc = h ? pvp : op, dd = h ? pvq : oq;
+    const T det = da * dd - db * dc;
+    const T inv = recip(det);
+    const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
+    const bool zero = l < t && (!(fabs(da) > eps * (fabs(da) + fabs(db))) ||
+                                !(fabs(det) > eps * fabs(da) * (fabs(dc) + fabs(dd))) || !isfinite(inv));
+    if (__ballot(zero) && ln == 0) piv[s] = 1;
+  }
   if (fwd && l < t) c.y[sP<S>(tb + l, s) + h] = y;
 }
 
