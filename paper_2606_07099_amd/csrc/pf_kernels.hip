@@ -683,6 +683,17 @@ __device__ __forceinline__ void ltail_bsolve(const Sym& m, const Dims& D, St<T>&
 // blocks, U rows and solved unknowns reach the other lanes by lane broadcast.
 // Same arithmetic, in the same order, as the sparse per-pivot elimination.
 
+// tail block row of a lane (lanes 2l and 2l + 1), made opaque to the
+// compiler at each use: otherwise the per-column lane masks of the unrolled
+// loops (l == j, l < j for every j) are hoisted out of the Newton loop and
+// live in spilled scalar registers, which costs more to reload than to
+// recompute
+__device__ __forceinline__ int lane_row(int ln) {
+  int l = ln >> 1;
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
 // register capacity of the dense tail, in block rows (one 32-dword register
 // tuple per scalar-row half)
 template <typename T>
@@ -713,7 +724,7 @@ template <typename T, int S>
 __device__ __forceinline__ void rt_load(const Sym& m, const Dims& D, const St<T>& c, int s, int l, int h,
                                         TailRow<T>& R) {
   R = TailRow<T>{};
-  const int t = D.tail_t;
+  const int t = __builtin_amdgcn_readfirstlane(D.tail_t);
   constexpr int C = tail_cap<T>();
   // eight columns at a time, their index and value loads issued together
 #pragma unroll
@@ -747,9 +758,9 @@ __device__ __forceinline__ void rt_load(const Sym& m, const Dims& D, const St<T>
 template <typename T, int S>
 __device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c, int s, int ln, bool fwd,
                                           int* piv, TailRow<T>& R) {
-  const int t = D.tail_t, tb = D.tail_base;
+  const int t = __builtin_amdgcn_readfirstlane(D.tail_t), tb = D.tail_base;
   if (t == 0) return;
-  const int l = ln >> 1, h = ln & 1;
+  const int l = lane_row(ln), h = ln & 1;
   rt_load<T, S>(m, D, c, s, l, h, R);
   T y = T(0);   // component h of the right-hand side of row l
   if (fwd && l < t) y = c.y[sP<S>(tb + l, s) + h];
@@ -822,8 +833,8 @@ __device__ __forceinline__ void rt_factor(const Sym& m, const Dims& D, St<T>& c,
 template <typename T, int S>
 __device__ __forceinline__ void rt_store(const Sym& m, const Dims& D, St<T>& c, int s, int ln,
                                          const TailRow<T>& R) {
-  const int t = D.tail_t, tb = D.tail_base;
-  const int l = ln >> 1, h = ln & 1;
+  const int t = __builtin_amdgcn_readfirstlane(D.tail_t), tb = D.tail_base;
+  const int l = lane_row(ln), h = ln & 1;
   constexpr int C = tail_cap<T>();
 #pragma unroll
   for (int jb = 0; jb < C; jb += 8) {
@@ -851,9 +862,9 @@ __device__ __forceinline__ void rt_store(const Sym& m, const Dims& D, St<T>& c, 
 template <typename T, int S>
 __device__ __forceinline__ void rt_fsolve(const Sym& m, const Dims& D, St<T>& c, int s, int ln,
                                           const TailRow<T>& R) {
-  const int t = D.tail_t, tb = D.tail_base;
+  const int t = __builtin_amdgcn_readfirstlane(D.tail_t), tb = D.tail_base;
   if (t == 0) return;
-  const int l = ln >> 1, h = ln & 1;
+  const int l = lane_row(ln), h = ln & 1;
   T y = T(0);
   if (l < t) {
     const int a = tb + l;
@@ -879,9 +890,9 @@ __device__ __forceinline__ void rt_fsolve(const Sym& m, const Dims& D, St<T>& c,
 template <typename T, int S>
 __device__ __forceinline__ void rt_bsolve(const Sym& m, const Dims& D, St<T>& c, int s, int ln,
                                           const TailRow<T>& R) {
-  const int t = D.tail_t, tb = D.tail_base;
+  const int t = __builtin_amdgcn_readfirstlane(D.tail_t), tb = D.tail_base;
   if (t == 0) return;
-  const int l = ln >> 1, h = ln & 1;
+  const int l = lane_row(ln), h = ln & 1;
   T y = T(0);
   if (l < t) y = c.y[sP<S>(tb + l, s) + h];
   const unsigned cm = __builtin_amdgcn_readfirstlane(m.tail_mask[t + 1]);   // columns with U blocks
@@ -1324,9 +1335,9 @@ __device__ __forceinline__ void phase_tsolve(const AdjSym& a, const Dims& D, St<
 // the terms on rows outside the tail), then L^T backward.
 template <typename T, int S>
 __device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const Dims& D, St<T>& c, int s, int ln) {
-  const int t = D.tail_t, tb = D.tail_base;
+  const int t = __builtin_amdgcn_readfirstlane(D.tail_t), tb = D.tail_base;
   if (t == 0) return;
-  const int l = ln >> 1, h = ln & 1;
+  const int l = lane_row(ln), h = ln & 1;
   TailRow<T> R = TailRow<T>{};
   constexpr int C = tail_cap<T>();
 #pragma unroll
