@@ -39,8 +39,8 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # Sources: profiles/k_newton_118bus_b1024_hbm_counters.md,
 # profiles/k_newton_1354bus_b4096_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "1692f9bb1a1c7b3af3ebfa339ee5374a9876a5f4bb937f81e570365d666d4310": {"c1": 7079607,
-                                                                         "c2": 46526455103},
+    "c6bd1413b77c79a37aeb9f96775563cbe6fe19e8ed5bf1ae1954597d92d00ab1": {"c1": 6940352,
+                                                                         "c2": 46516597873},
 }
 
 
