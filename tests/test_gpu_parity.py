@@ -268,11 +268,13 @@ def test_ragged_and_single_scenario_batches(batch, device):
     _check_solution(net, sc, which, res, oracle, tol, iters_slack=1)
 
 
-def test_zero_admittance_branch_gives_zero_pivot_status(device):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_zero_admittance_branch_gives_zero_pivot_status(device, precision):
     """A branch whose admittance entries are present in the pattern but zero
     leaves its far bus with an all-zero Jacobian block: the factorisation
     reports status 3 (zero pivot) for that scenario, and the dense oracle
-    Jacobian is exactly singular there."""
+    Jacobian is exactly singular there.  Two block rows: no dense tail, so
+    this covers the pivot test of the level-scheduled factorisation."""
     import torch
     from paper_2606_07099_amd import PFTemplate
     # slack 0 -- PQ 1 -- PQ 2, the 1-2 branch with zero admittance
@@ -285,7 +287,7 @@ def test_zero_admittance_branch_gives_zero_pivot_status(device):
     g = np.array([Yd[r, c].real for r, c in zip([0, 0, 1, 1, 1, 2, 2], indices)])
     b = np.array([Yd[r, c].imag for r, c in zip([0, 0, 1, 1, 1, 2, 2], indices)])
     bt = np.array([2, 0, 0], np.int32)
-    tpl = PFTemplate(3, bt, indptr, indices, g, b, 2, tol=1e-10)
+    tpl = PFTemplate(3, bt, indptr, indices, g, b, 2, tol=1e-10, precision=precision)
     pd = torch.tensor([[0.0, 0.3, 0.0], [0.0, 0.3, 0.2]], dtype=torch.float64, device=device)
     qd = 0.1 * pd
     vset = torch.ones_like(pd)
@@ -293,6 +295,46 @@ def test_zero_admittance_branch_gives_zero_pivot_status(device):
     assert status[0] == 3 and status[1] == 3
     from oracle.newton import Index, j1
     J = j1(Yd, np.ones(3, complex), Index.of(bt))
+    assert np.linalg.matrix_rank(J) < J.shape[0]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_zero_pivot_inside_the_dense_tail(device, precision):
+    """A path slack - 1 - 2 - 3 - 4 - 5 whose last branch has zero admittance:
+    the five block rows form a chain of single-row levels, all of them in
+    the dense tail, and the far bus's block is exactly zero, so the tail's
+    pivot test (run once after its elimination) must report status 3 for
+    every scenario; the dense oracle Jacobian is singular."""
+    import torch
+    from paper_2606_07099_amd import PFTemplate
+    n = 6
+    y = 1.0 / complex(0.01, 0.1)
+    Yd = np.zeros((n, n), complex)
+    for i in range(n - 2):   # branches (0,1) .. (3,4); (4,5) has zero admittance
+        Yd[i, i] += y
+        Yd[i + 1, i + 1] += y
+        Yd[i, i + 1] -= y
+        Yd[i + 1, i] -= y
+    rows = [(i, j) for i in range(n) for j in range(n) if abs(i - j) <= 1]
+    indptr = np.zeros(n + 1, np.int32)
+    for i, _ in rows:
+        indptr[i + 1] += 1
+    indptr = np.cumsum(indptr).astype(np.int32)
+    indices = np.array([j for _, j in rows], np.int32)
+    g = np.array([Yd[i, j].real for i, j in rows])
+    b = np.array([Yd[i, j].imag for i, j in rows])
+    bt = np.array([2, 0, 0, 0, 0, 0], np.int32)
+    tpl = PFTemplate(n, bt, indptr, indices, g, b, 3, tol=1e-10, precision=precision)
+    pd = torch.tensor([[0.0, 0.1, 0.1, 0.1, 0.1, 0.0],
+                       [0.0, 0.2, 0.1, 0.0, 0.1, 0.0],
+                       [0.0, 0.0, 0.0, 0.0, 0.0, 0.0]], dtype=torch.float64, device=device)
+    qd = 0.1 * pd
+    vset = torch.ones_like(pd)
+    vm, va, iters, status, fn = (x.cpu().numpy() for x in tpl.solve(pd, qd, None, vset))
+    # the zero-load scenario converges at the flat start, before any factorisation
+    assert status.tolist() == [3, 3, 0]
+    from oracle.newton import Index, j1
+    J = j1(Yd, np.ones(n, complex), Index.of(bt))
     assert np.linalg.matrix_rank(J) < J.shape[0]
 
 
