@@ -39,8 +39,8 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # Sources: profiles/k_newton_118bus_b1024_hbm_counters.md,
 # profiles/k_newton_1354bus_b4096_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "c6bd1413b77c79a37aeb9f96775563cbe6fe19e8ed5bf1ae1954597d92d00ab1": {"c1": 6940352,
-                                                                         "c2": 46516597873},
+    "54aa4290f59904b38a63c93c86efd80e2d2982242dc8796505c573aabb1edc36": {"c1": 6940356,
+                                                                         "c2": 46518049629},
 }
 
 

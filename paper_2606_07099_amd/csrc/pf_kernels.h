@@ -97,16 +97,16 @@ struct KParams {
 };
 
 // LDS-resident slices: one wavefront per scenario for the register-resident
-// dense tail, at most 4 scenarios per workgroup.  The Newton kernel runs 512
-// threads with FP32 factors (the extra wavefronts hide LDS latency in the
-// barrier-separated phases) and 256 with FP64 factors (whose register tail
-// needs more than the 256 registers a 512-thread workgroup leaves a
-// wavefront); the adjoint runs kResThreads.
+// dense tail, at most 4 scenarios per workgroup.  The Newton kernel and the
+// adjoint run kResThreads: the wavefronts beyond the slice's tails hide LDS
+// latency in the barrier-separated phases (with FP64 factors the register
+// tail then fits the 256 registers a 512-thread workgroup leaves a
+// wavefront with a few spilled values outside the inner loops).
 constexpr int kResThreads = 512;
 constexpr int kResMaxSlice = 4;
 template <typename T>
-constexpr int res_newton_threads() { return sizeof(T) == 4 ? 512 : 256; }
-inline int res_newton_threads(bool fp32) { return fp32 ? 512 : 256; }
+constexpr int res_newton_threads() { return kResThreads; }
+inline int res_newton_threads(bool) { return kResThreads; }
 
 // slice = scenarios per workgroup: 1, 2 or 4 when LDS-resident, up to 16 otherwise.
 hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds,
