@@ -411,3 +411,86 @@ def test_adjoint_matches_central_differences_on_14_bus():
             fd = fd_gradient(Y, net.bus_type, sc.pd[b], sc.qd[b], sc.pg[b], sc.vset[b], which, coords)
             an = getattr(g, which)[coords]
             assert np.linalg.norm(an - fd) <= 1e-6 * max(np.linalg.norm(fd), 1e-3), which
+
+
+# ---------------------------------------------------------------- statuses
+#
+# Readings of the stopping rule (the paper gives only the tolerance): the
+# test ||F1||_inf < tol runs before every update, iters counts the updates
+# applied, a scenario still at or above tol after max_iter updates stops
+# with status 1, and a non-finite mismatch stops it with status 2.
+
+def _two_bus_pq_step(P, Q, R, X, U, d):
+    """One Newton update of the 2-bus slack-PQ network from (|V2|, theta2),
+    with F = spec - calc formed from the branch flow V2 conj((V2 - 1)/z)
+    and a central-difference Jacobian (independent of the oracle's)."""
+    z = complex(R, X)
+
+    def F(u):
+        V2 = u[1] * np.exp(1j * u[0])
+        S2 = V2 * np.conj((V2 - 1.0) / z)
+        return np.array([-P - S2.real, -Q - S2.imag])
+
+    u = np.array([d, U])
+    h = 1e-7
+    J = np.column_stack([(F(u + h * e) - F(u - h * e)) / (2 * h) for e in np.eye(2)])
+    du = np.linalg.solve(J, -F(u))
+    return u[1] + du[1], u[0] + du[0]
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_overload_stops_after_exactly_max_iter_updates(k):
+    """Load beyond the 2-bus loadability limit (negative discriminant of the
+    quartic in |V2|^2, so no power-flow solution exists): Newton cannot
+    converge, and with max_iter = k the oracle returns status 1 after exactly
+    k updates, the k-th one being a Newton step from the state after k - 1.
+    (k <= 2: the third step would start from a negative |V2|, outside the
+    domain where the oracle's derivative forms, which divide by |V|, are
+    those of the magnitude variable.)"""
+    P, Q, R, X = 5.0, 2.0, 0.02, 0.1
+    a = P * R + Q * X
+    assert (1 - 2 * a) ** 2 - 4 * (P * P + Q * Q) * (R * R + X * X) < 0
+    bt, Y = two_bus(R, X, PQ)
+    args = (Y, bt, np.array([0.0, P]), np.array([0.0, Q]), np.zeros(2), np.ones(2))
+    r = newton(*args, tol=1e-8, max_iter=k)
+    prev = newton(*args, tol=1e-8, max_iter=k - 1)
+    assert r.status == 1 and r.iters == k and len(r.history) == k + 1
+    assert prev.status == 1 and prev.iters == k - 1
+    U, d = _two_bus_pq_step(P, Q, R, X, prev.vm[1], prev.va[1])
+    assert abs(r.vm[1] - U) < 1e-6 * max(1.0, abs(U)) and abs(r.va[1] - d) < 1e-6 * max(1.0, abs(d))
+    # the reported mismatch is the one at the returned state
+    S2 = r.vm[1] * np.exp(1j * r.va[1]) * np.conj((r.vm[1] * np.exp(1j * r.va[1]) - 1.0) / complex(R, X))
+    assert abs(r.final_mismatch - max(abs(-P - S2.real), abs(-Q - S2.imag))) < 1e-9 * max(1.0, r.final_mismatch)
+
+
+def test_max_iter_zero_only_evaluates_the_flat_start():
+    """max_iter = 0: no update, status 1 for a loaded network, and the
+    reported mismatch is the flat-start one, which without line charging is
+    the specified injection itself (the calculated injection is 0)."""
+    spec, net, sc = make_case("c0", batch=1)
+    Y = ybus_dense(net.n_bus, net.f, net.t, net.r, net.x, np.zeros_like(net.bc))
+    vset = np.ones(net.n_bus)
+    r = newton(Y, net.bus_type, sc.pd[0], sc.qd[0], sc.pg[0], vset, max_iter=0)
+    assert r.status == 1 and r.iters == 0
+    p, q = specified(sc.pd[0], sc.qd[0], sc.pg[0], net.bus_type)
+    idx = Index.of(net.bus_type)
+    expect = max(np.abs(p[idx.pvpq]).max(), np.abs(q[idx.pq]).max())
+    assert abs(r.final_mismatch - expect) < 1e-13
+    assert np.all(r.vm == vset) and np.all(r.va == 0.0)
+
+
+@pytest.mark.parametrize("where", ["pd", "qd", "pg"])
+def test_non_finite_input_stops_at_the_flat_start_with_status_2(where):
+    spec, net, sc = make_case("c0", batch=1)
+    Y = ybus_of(net)
+    x = {k: getattr(sc, k)[0].copy() for k in ("pd", "qd", "pg", "vset")}
+    bus = int(np.flatnonzero(net.bus_type == (PV if where == "pg" else PQ))[0])
+    x[where][bus] = np.nan
+    r = newton(Y, net.bus_type, x["pd"], x["qd"], x["pg"], x["vset"])
+    assert r.status == 2 and r.iters == 0 and np.isnan(r.final_mismatch)
+    # generation on a PQ bus is not read (it is zero by definition), so a NaN
+    # there changes nothing
+    x = {k: getattr(sc, k)[0].copy() for k in ("pd", "qd", "pg", "vset")}
+    x["pg"][int(np.flatnonzero(net.bus_type == PQ)[0])] = np.nan
+    r = newton(Y, net.bus_type, x["pd"], x["qd"], x["pg"], x["vset"])
+    assert r.status == CONVERGED
