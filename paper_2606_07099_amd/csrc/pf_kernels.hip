@@ -433,6 +433,11 @@ __device__ __forceinline__ void phase_factor(const Sym& m, const Dims& D, St<T>&
       }
       if (e == 0) {
         if (tk.z >= 0) {
+          // a task that inverts its row's pivot block eliminates only
+          // children of the row in the elimination tree, whose first U
+          // column is the row itself: the diagonal is target 0 of every
+          // step, updated by this lane, so only the other lanes' targets of
+          // earlier steps (several steps) need the fence before it is read
           if (se - tk.w > 1 && E > 1) wave_order<RES>();
           const Blk<T> Dk = ld_blk(W + sB<S>(tk.z, s));
           const T det = Dk.a * Dk.d - Dk.b * Dk.c;

@@ -115,6 +115,8 @@ class PFTemplate:
         self._ix, ixp = _i32(indices)
         self._g, gp = _f64(g)
         self._b, bp = _f64(b)
+        import torch
+        self.device = torch.cuda.current_device() if torch.cuda.is_available() else 0
         h = ctypes.c_void_p()
         check(L.pf_template_build(self.n_bus, btp, ipp, ixp, gp, bp, self.batch, ctypes.byref(opt),
                                   ctypes.byref(h)))
@@ -148,15 +150,20 @@ class PFTemplate:
         return self.info()["n_j"]
 
     # ------------------------------------------------------------------
-    def _check(self, name, x, rows=None):
+    def _check(self, name, x, rows=None, cols=None):
+        """A float64 contiguous CUDA tensor on the template's device with at
+        least ``rows`` rows of ``cols`` columns (default: batch x n_bus)."""
         import torch
         rows = self.batch if rows is None else rows
+        cols = self.n_bus if cols is None else cols
         if not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_cuda:
             raise TypeError(f"{name} must be a float64 CUDA tensor")
+        if x.device.index != self.device:
+            raise ValueError(f"{name} is on {x.device}, the template on cuda:{self.device}")
         if not x.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
-        if x.dim() != 2 or x.shape[0] < rows or x.shape[1] != self.n_bus:
-            raise ValueError(f"{name} must have shape [{rows}, {self.n_bus}], got {tuple(x.shape)}")
+        if x.dim() != 2 or x.shape[0] < rows or x.shape[1] != cols:
+            raise ValueError(f"{name} must have shape [{rows}, {cols}], got {tuple(x.shape)}")
         return ctypes.c_void_p(x.data_ptr())
 
     def solve(self, pd, qd, pg, vset, *, out=None, stream=None):
@@ -172,6 +179,12 @@ class PFTemplate:
             fn = torch.empty(self.batch, dtype=torch.float64, device=dev)
         else:
             vm, va, iters, status, fn = out
+        for nm, x, dt in (("iters", iters, torch.int32), ("status", status, torch.int32),
+                          ("final_mismatch", fn, torch.float64)):
+            if (not isinstance(x, torch.Tensor) or x.dtype != dt or not x.is_cuda or not x.is_contiguous()
+                    or x.device.index != self.device or x.numel() < self.batch):
+                raise ValueError(f"{nm} must be a contiguous {dt} CUDA tensor of {self.batch} elements "
+                                 f"on cuda:{self.device}")
         args = [self._check("pd", pd), self._check("qd", qd),
                 self._check("pg", pg) if pg is not None else ctypes.c_void_p(0),
                 self._check("vset", vset), self._check("vm", vm), self._check("va", va)]
@@ -227,10 +240,10 @@ class PFTemplate:
         value array in place instead of allocating a new one."""
         import torch
         count = int(vm.shape[0])
-        if vm.dtype != torch.float64 or not vm.is_contiguous() or tuple(vm.shape) != (count, self.n_bus):
-            raise ValueError("vm must be contiguous float64 [count, n_bus]")
-        if va.dtype != torch.float64 or not va.is_contiguous() or tuple(va.shape) != (count, self.n_bus):
-            raise ValueError("va must be contiguous float64 [count, n_bus]")
+        self._check("vm", vm, count)
+        self._check("va", va, count)
+        if tuple(va.shape) != tuple(vm.shape):
+            raise ValueError("vm and va must have the same shape [count, n_bus]")
         cache = self.__dict__.setdefault("_op_cache", {})
         key = (int(which), count, vm.device)
         if key not in cache:
@@ -265,9 +278,9 @@ class PFTemplate:
         out = torch.empty(shape, dtype=torch.float64, device=vm.device)
         r = ctypes.c_void_p(0)
         if rhs is not None:
-            if rhs.dtype != torch.float64 or not rhs.is_contiguous() or tuple(rhs.shape[1:]) != (nj,):
-                raise ValueError("rhs must be contiguous float64 [count, n_j]")
-            r = ctypes.c_void_p(rhs.data_ptr())
+            r = self._check("rhs", rhs, count, nj)
+        elif mode == PF_EVAL_ADJOINT:
+            raise ValueError("PF_EVAL_ADJOINT needs rhs [count, n_j]")
         check(lib().pf_eval_batch(self._h, int(mode), count,
                                   self._check("pd", pd, count), self._check("qd", qd, count),
                                   self._check("pg", pg, count) if pg is not None else ctypes.c_void_p(0),

@@ -1,5 +1,5 @@
 """Synthetic end-to-end training through the PF layer: the analogue of the
-paper's layer-training experiments (Sec. IV-B, Tables V and VI), with a
+paper's layer-training experiments (Sec. IV-C, Tables V and VI), with a
 synthetic task in place of the DC3 and DeepLDE models and their datasets.
 
 A small MLP maps each scenario's loads to the decision block x (eq. ynn):
