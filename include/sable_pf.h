@@ -85,8 +85,8 @@ typedef struct {
   int32_t keep_factors;  /* 1 (default): after convergence re-evaluate J1 and refactor
                             at the solution and keep the factors for pf_adjoint_batch */
   int32_t block_threads; /* threads per workgroup, 0 = automatic (64..1024); LDS-resident
-                            slices always run 512 threads (PF_MIXED) or 256 (PF_FP64),
-                            so any other nonzero value selects HBM-resident slices */
+                            slices always run 512 threads, so any other nonzero value
+                            selects HBM-resident slices */
   int32_t refine_adaptive; /* PF_MIXED forward solve: 0 (default) applies all refine_steps
                             refinement solves; 1 computes the FP64 residual r of the
                             current correction and refines only while
@@ -157,6 +157,12 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
 
 /* Sizes of the analysis.  Host-only, never touches the device. */
 int pf_template_info(const pf_template* tpl, pf_template_stats* out);
+
+/* The 2x2-block pattern of L+U in the library's storage order (one-time
+   symbolic analysis, Sec. III-B): host outputs row_bus[nnzb_lu] and
+   col_bus[nnzb_lu], the buses of each block's row and column.  Host-only.
+   Errors: PF_EINVAL. */
+int pf_template_block_pattern(const pf_template* tpl, int32_t* row_bus, int32_t* col_bus);
 
 /* Releases the template and its device memory (synchronises the device).
    NULL is accepted. */
@@ -268,7 +274,8 @@ int pf_adjoint_completed_batch(pf_template* tpl, const double* g_vm, const doubl
  * One scenario's pattern is built once; the batch-global operator is the
  * block-diagonal embedding of that pattern (eq. BDE_global: scenario b's block
  * at row offset b*n_rows and column offset b*n_cols), whose CSR value array is
- * exactly values[count][nnz] below.
+ * exactly values[count][nnz] below (pf_operator_bde_csr writes its row
+ * pointers and column indices).
  */
 #define PF_OP_BASE 0
 #define PF_OP_J1 1
@@ -297,17 +304,30 @@ int pf_operator_pattern(int32_t n_bus, const int32_t* bus_type, const int32_t* y
  * (vm, va) (device [count][n_bus], FP64): device output values[count][nnz],
  * in the order of pf_operator_pattern's CSR, evaluated in FP64 (Algorithm 1's
  * entry formulas; selectors are 1).  count may exceed the template's batch:
- * only the template's pattern is used, not its workspace.  The first call on
- * a template allocates its small operator tables and a buffer of
- * 32 * count * n_bus bytes for the per-bus voltages and injections (device memory,
- * released by pf_template_destroy); a later call with a larger count grows
- * that buffer (after a device synchronisation), any other call allocates
- * nothing.  Calls on one template share the buffer: calls that overlap on
- * different streams race.  Asynchronous on hip_stream.  Errors: PF_EINVAL,
- * PF_ENOMEM, PF_EHIP.
+ * only the template's pattern is used, not its workspace.  The operator
+ * tables are built with the template; the first call allocates a buffer of
+ * 32 * count * n_bus bytes for the per-bus voltages and injections (device
+ * memory, released by pf_template_destroy); a later call with a larger count
+ * grows that buffer (after a device synchronisation), any other call
+ * allocates nothing.  Calls on one template share the buffer: calls that
+ * overlap on different streams race.  Asynchronous on hip_stream.
+ * Errors: PF_EINVAL, PF_ENOMEM, PF_EHIP.
  */
 int pf_operator_values(pf_template* tpl, int32_t which, int32_t count, const double* vm,
                        const double* va, double* values, void* hip_stream);
+
+/*
+ * Row pointers and column indices of the batch-global operator `which` for
+ * `count` scenarios: the block-diagonal embedding of one scenario's pattern
+ * (eq. BDE_global; scenario b's block at row offset b * n_rows and column
+ * offset b * n_cols of pf_operator_pattern, its values at offset b * nnz, so
+ * values[count][nnz] of pf_operator_values is this CSR's value array).
+ * Device outputs, int64: crow[count * n_rows + 1], col[count * nnz]
+ * (caller-owned).  count = 0 writes crow[0] = 0 only.  Asynchronous on
+ * hip_stream; allocates nothing.  Errors: PF_EINVAL, PF_EHIP.
+ */
+int pf_operator_bde_csr(pf_template* tpl, int32_t which, int32_t count, int64_t* crow, int64_t* col,
+                        void* hip_stream);
 
 /*
  * Evaluation entry points at a GIVEN state (vm, va device [batch][n_bus]),
@@ -322,6 +342,15 @@ int pf_operator_values(pf_template* tpl, int32_t which, int32_t count, const dou
  *                                              precision (+ refinement if mixed)
  *   PF_EVAL_ADJOINT:  out[count][n_j]        = lambda solving J1^T lambda = rhs,
  *                     rhs[count][n_j] given in the unknown ordering
+ *   PF_EVAL_FILL:     out[count][4 nnzb_lu]  = the values the Jacobian value
+ *                     update (Algorithm 1) writes into the LU positions before
+ *                     the factorisation, in the library's block order
+ *                     (pf_template_block_pattern), each 2x2 block row-major
+ *                     with rows (dP_i, dQ_i) and columns (theta_j, |V|_j) of
+ *                     its bus pair; a PV bus's dQ row and |V| column are
+ *                     padding (zero, with 1 on its diagonal block's |V|
+ *                     entry), fill-in blocks are zero; converted from the
+ *                     factor precision to FP64
  * pd/qd/pg/vset as for pf_solve_batch (the Jacobian and the adjoint solve do
  * not read them but they must be valid).  rhs is only read by
  * PF_EVAL_ADJOINT (may be NULL otherwise).
@@ -330,6 +359,7 @@ int pf_operator_values(pf_template* tpl, int32_t which, int32_t count, const dou
 #define PF_EVAL_JACOBIAN 1
 #define PF_EVAL_STEP 2
 #define PF_EVAL_ADJOINT 3
+#define PF_EVAL_FILL 4
 int pf_eval_batch(pf_template* tpl, int32_t mode, int32_t count, const double* pd,
                   const double* qd, const double* pg, const double* vset, const double* vm,
                   const double* va, const double* rhs, double* out, void* hip_stream);

@@ -15,13 +15,13 @@ PF_OK, PF_EINVAL, PF_ETOPOLOGY, PF_ENOMEM, PF_EHIP, PF_ESTATE = 0, -1, -2, -3, -
 PF_BUS_PQ, PF_BUS_PV, PF_BUS_SLACK = 0, 1, 2
 PF_FP64, PF_MIXED = 0, 1
 PF_STATUS_CONVERGED, PF_STATUS_MAX_ITER, PF_STATUS_NON_FINITE, PF_STATUS_ZERO_PIVOT = 0, 1, 2, 3
-PF_EVAL_MISMATCH, PF_EVAL_JACOBIAN, PF_EVAL_STEP, PF_EVAL_ADJOINT = 0, 1, 2, 3
+PF_EVAL_MISMATCH, PF_EVAL_JACOBIAN, PF_EVAL_STEP, PF_EVAL_ADJOINT, PF_EVAL_FILL = 0, 1, 2, 3, 4
 PF_OP_BASE, PF_OP_J1, PF_OP_J1T, PF_OP_J2T, PF_OP_J3T = 0, 1, 2, 3, 4
 
 EXPORTED = ("pf_default_options", "pf_last_error", "pf_ybus_from_branches", "pf_template_build",
             "pf_template_info", "pf_template_destroy", "pf_symbolic_analyze", "pf_solve_batch",
             "pf_adjoint_batch", "pf_eval_batch", "pf_recover_batch", "pf_adjoint_completed_batch",
-            "pf_operator_pattern", "pf_operator_values")
+            "pf_operator_pattern", "pf_operator_values", "pf_operator_bde_csr", "pf_template_block_pattern")
 
 
 class PFOptions(ctypes.Structure):
@@ -83,10 +83,9 @@ def lib():
     L.pf_solve_batch.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.pf_adjoint_batch.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P]
     L.pf_eval_batch.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
-    for name in ("pf_ybus_from_branches", "pf_template_build", "pf_template_info",
-                 "pf_template_destroy", "pf_symbolic_analyze", "pf_solve_batch",
-                 "pf_adjoint_batch", "pf_eval_batch", "pf_recover_batch", "pf_adjoint_completed_batch",
-            "pf_operator_pattern", "pf_operator_values"):
+    L.pf_operator_bde_csr.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]
+    L.pf_template_block_pattern.argtypes = [_P, _I32P, _I32P]
+    for name in EXPORTED[2:]:
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -46,12 +46,17 @@ struct pf_template {
   void* wsl_t = nullptr;
   size_t ws_bytes = 0;
   bool have_factors = false;
-  // operator export tables, built on first use: the base entries (int4
-  // each), then the source map of every operator
+  // operator export tables, built with the template: the base entries
+  // (int4 each), then per operator its source map, CSR row pointers and
+  // column indices (one scenario's pattern)
   void* d_ops = nullptr;
   int32_t op_nbase = 0;
   int32_t op_off[sable::OP_COUNT] = {};
   int32_t op_nnz[sable::OP_COUNT] = {};
+  int32_t op_ip_off[sable::OP_COUNT] = {};
+  int32_t op_ix_off[sable::OP_COUNT] = {};
+  int32_t op_rows[sable::OP_COUNT] = {};
+  int32_t op_cols[sable::OP_COUNT] = {};
   double* d_opef = nullptr;   // per-bus state (e, f, P, Q) of the last operator refresh
   size_t opef_count = 0;      // scenarios it holds
 };
@@ -210,6 +215,41 @@ sable::KParams base_params(const pf_template* t) {
   return kp;
 }
 
+// the operator tables of a template: one device buffer of int32
+int build_operator_tables(pf_template* t) {
+  const sable::Symbolic& S = t->sym;
+  sable::OperatorSet ops;
+  std::string err;
+  const int rc = sable::build_operators(S.n_bus, S.bus_type.data(), S.y_rp.data(), S.y_ci.data(), ops, err);
+  if (rc != PF_OK) return fail(rc, "operator tables: " + err);
+  std::vector<int32_t> buf;
+  for (const sable::BaseEntry& e : ops.base) buf.insert(buf.end(), {e.kind, e.i, e.j, e.q});
+  t->op_nbase = (int32_t)ops.base.size();
+  for (int k = 0; k < sable::OP_COUNT; ++k) {
+    const sable::OperatorPattern& op = ops.op[k];
+    t->op_off[k] = (int32_t)buf.size();
+    t->op_nnz[k] = (int32_t)op.src.size();
+    buf.insert(buf.end(), op.src.begin(), op.src.end());
+    t->op_ip_off[k] = (int32_t)buf.size();
+    buf.insert(buf.end(), op.indptr.begin(), op.indptr.end());
+    t->op_ix_off[k] = (int32_t)buf.size();
+    buf.insert(buf.end(), op.indices.begin(), op.indices.end());
+    t->op_rows[k] = op.rows;
+    t->op_cols[k] = op.cols;
+  }
+  void* d = nullptr;
+  if (hipMalloc(&d, buf.size() * sizeof(int32_t)) != hipSuccess)
+    return fail(PF_ENOMEM, "pf_template_build: device allocation (operator tables)");
+  hipError_t he = hipMemcpy(d, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (he != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(he, "pf_template_build: operator table upload");
+  }
+  t->d_ops = d;
+  t->ws_bytes += buf.size() * sizeof(int32_t);
+  return PF_OK;
+}
+
 int adjoint_impl(const char* name, pf_template* t, const double* g_vm, const double* g_va,
                  const double* g_pgo, const double* g_qgo, double* g_pd, double* g_qd, double* g_pg,
                  double* g_vset, void* hip_stream) {
@@ -234,6 +274,38 @@ int adjoint_impl(const char* name, pf_template* t, const double* g_vm, const dou
 }
 
 }  // namespace
+
+namespace sable {
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int operator_params(pf_template* t, int which, int count, const double* vm, const double* va, double* values,
+                    const char* name, OpParams& p, int& device) {
+  g_err.clear();
+  const std::string nm(name);
+  if (!t) return fail(PF_EINVAL, nm + ": template is NULL");
+  if (which < 0 || which >= OP_COUNT) return fail(PF_EINVAL, nm + ": unknown operator");
+  if (count < 0) return fail(PF_EINVAL, nm + ": negative count");
+  if (count > 0 && (!vm || !va || !values)) return fail(PF_EINVAL, nm + ": NULL array");
+  const unsigned char* img = static_cast<const unsigned char*>(t->d_sym);
+  p = OpParams{};
+  p.base = static_cast<const int4*>(t->d_ops);
+  p.src = static_cast<const int*>(t->d_ops) + t->op_off[which];
+  p.y_rp = reinterpret_cast<const int*>(img + t->so.y_rp);
+  p.y_ci = reinterpret_cast<const int*>(img + t->so.y_ci);
+  p.y_g = reinterpret_cast<const double*>(img + t->so.y_g);
+  p.y_b = reinterpret_cast<const double*>(img + t->so.y_b);
+  p.vm = vm;
+  p.va = va;
+  p.values = values;
+  p.nnz = t->op_nnz[which];
+  p.n_bus = t->sym.n_bus;
+  p.count = count;
+  device = t->device;
+  return PF_OK;
+}
+
+}  // namespace sable
 
 extern "C" {
 
@@ -490,6 +562,12 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he != hipSuccess) { pf_template_destroy(t); return hip_fail(he, "pf_template_build: set-up"); }
   t->ws_bytes = pk.buf.size() + bd + bt + bi + bsl;
+  rc = build_operator_tables(t);
+  if (rc != PF_OK) {
+    const std::string msg = g_err;
+    pf_template_destroy(t);
+    return fail(rc, msg);
+  }
   *out = t;
   return PF_OK;
 }
@@ -601,6 +679,10 @@ int pf_eval_batch(pf_template* t, int32_t mode, int32_t count, const double* pd,
     case PF_EVAL_JACOBIAN:
       he = sable::launch_jacobian_dense(kp, count, st);
       break;
+    case PF_EVAL_FILL:
+      kp.mode = sable::MODE_EVAL_FILL;
+      he = sable::launch_newton(kp, t->fp32, t->slice, grid, t->nt, t->lds_bytes, t->lds_res, st);
+      break;
     case PF_EVAL_ADJOINT:
       kp.mode = sable::MODE_EVAL_FACTOR;
       he = sable::launch_newton(kp, t->fp32, t->slice, grid, t->nt, t->lds_bytes, t->lds_res, st);
@@ -649,36 +731,11 @@ int pf_operator_pattern(int32_t n_bus, const int32_t* bus_type, const int32_t* y
 
 int pf_operator_values(pf_template* t, int32_t which, int32_t count, const double* vm, const double* va,
                        double* values, void* hip_stream) {
-  g_err.clear();
-  if (!t) return fail(PF_EINVAL, "pf_operator_values: template is NULL");
-  if (which < 0 || which >= sable::OP_COUNT) return fail(PF_EINVAL, "pf_operator_values: unknown operator");
-  if (count < 0) return fail(PF_EINVAL, "pf_operator_values: negative count");
-  if (count > 0 && (!vm || !va || !values)) return fail(PF_EINVAL, "pf_operator_values: NULL array");
-  DeviceGuard g(t->device);
-  if (!t->d_ops) {
-    const sable::Symbolic& S = t->sym;
-    sable::OperatorSet ops;
-    std::string err;
-    const int rc = sable::build_operators(S.n_bus, S.bus_type.data(), S.y_rp.data(), S.y_ci.data(), ops, err);
-    if (rc != PF_OK) return fail(rc, "pf_operator_values: " + err);
-    std::vector<int32_t> buf;
-    for (const sable::BaseEntry& e : ops.base) buf.insert(buf.end(), {e.kind, e.i, e.j, e.q});
-    t->op_nbase = (int32_t)ops.base.size();
-    for (int k = 0; k < sable::OP_COUNT; ++k) {
-      t->op_off[k] = (int32_t)buf.size();
-      t->op_nnz[k] = (int32_t)ops.op[k].src.size();
-      buf.insert(buf.end(), ops.op[k].src.begin(), ops.op[k].src.end());
-    }
-    void* d = nullptr;
-    hipError_t he = hipMalloc(&d, buf.size() * sizeof(int32_t));
-    if (he != hipSuccess) return fail(PF_ENOMEM, "pf_operator_values: device allocation (operator tables)");
-    he = hipMemcpy(d, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-    if (he != hipSuccess) {
-      (void)hipFree(d);
-      return hip_fail(he, "pf_operator_values: copy");
-    }
-    t->d_ops = d;
-  }
+  sable::OpParams p{};
+  int dev = 0;
+  int rc = sable::operator_params(t, which, count, vm, va, values, "pf_operator_values", p, dev);
+  if (rc != PF_OK) return rc;
+  DeviceGuard g(dev);
   if ((size_t)count > t->opef_count) {   // grow the state buffer (previous work may still read it)
     (void)hipDeviceSynchronize();
     if (t->d_opef) (void)hipFree(t->d_opef);
@@ -691,23 +748,37 @@ int pf_operator_values(pf_template* t, int32_t which, int32_t count, const doubl
     }
     t->opef_count = (size_t)count;
   }
-  const unsigned char* img = static_cast<const unsigned char*>(t->d_sym);
-  sable::OpParams p{};
-  p.base = static_cast<const int4*>(t->d_ops);
-  p.src = static_cast<const int*>(t->d_ops) + t->op_off[which];
-  p.y_rp = reinterpret_cast<const int*>(img + t->so.y_rp);
-  p.y_ci = reinterpret_cast<const int*>(img + t->so.y_ci);
-  p.y_g = reinterpret_cast<const double*>(img + t->so.y_g);
-  p.y_b = reinterpret_cast<const double*>(img + t->so.y_b);
-  p.vm = vm;
-  p.va = va;
   p.ef = t->d_opef;
-  p.values = values;
-  p.nnz = t->op_nnz[which];
-  p.n_bus = t->sym.n_bus;
-  p.count = count;
   hipError_t he = sable::launch_operator_values(p, static_cast<hipStream_t>(hip_stream));
   if (he != hipSuccess) return hip_fail(he, "pf_operator_values: launch");
+  return PF_OK;
+}
+
+int pf_operator_bde_csr(pf_template* t, int32_t which, int32_t count, int64_t* crow, int64_t* col,
+                        void* hip_stream) {
+  g_err.clear();
+  if (!t) return fail(PF_EINVAL, "pf_operator_bde_csr: template is NULL");
+  if (which < 0 || which >= sable::OP_COUNT) return fail(PF_EINVAL, "pf_operator_bde_csr: unknown operator");
+  if (count < 0) return fail(PF_EINVAL, "pf_operator_bde_csr: negative count");
+  if (!crow || (count > 0 && t->op_nnz[which] > 0 && !col))
+    return fail(PF_EINVAL, "pf_operator_bde_csr: NULL output array");
+  DeviceGuard g(t->device);
+  const int32_t* d = static_cast<const int32_t*>(t->d_ops);
+  hipError_t he = sable::launch_bde_csr(d + t->op_ip_off[which], d + t->op_ix_off[which], t->op_rows[which],
+                                        t->op_cols[which], t->op_nnz[which], count, crow, col,
+                                        static_cast<hipStream_t>(hip_stream));
+  if (he != hipSuccess) return hip_fail(he, "pf_operator_bde_csr: launch");
+  return PF_OK;
+}
+
+int pf_template_block_pattern(const pf_template* t, int32_t* row_bus, int32_t* col_bus) {
+  g_err.clear();
+  if (!t || !row_bus || !col_bus) return fail(PF_EINVAL, "pf_template_block_pattern: NULL argument");
+  const sable::Symbolic& S = t->sym;
+  for (int32_t p = 0; p < S.nnzb(); ++p) {
+    row_bus[p] = S.blk_bus[S.prow[p]];
+    col_bus[p] = S.blk_bus[S.ci[p]];
+  }
   return PF_OK;
 }
 

@@ -15,6 +15,7 @@ enum Mode : int {
   MODE_EVAL_STEP = 2,      // Newton correction at a given state
   MODE_EVAL_FACTOR = 3,    // factor J1 at a given state and keep it
   MODE_EVAL_ADJOINT = 4,   // adjoint solve with a given right-hand side
+  MODE_EVAL_FILL = 5,      // the Jacobian values in the LU positions, before factorisation
 };
 
 // LDS scratch at the start of every kernel's dynamic LDS: per-(wave,

@@ -1094,6 +1094,10 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       }
     }
     if (kp.mode == MODE_EVAL_MISMATCH || kp.mode == MODE_EVAL_FACTOR) break;
+    if (kp.mode == MODE_EVAL_FILL) {
+      phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
+      break;
+    }
     if (!act) break;
     for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
     phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
@@ -1185,6 +1189,13 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       if (kp.iters_out) kp.iters_out[b] = s_it[tid];
       if (kp.status_out) kp.status_out[b] = s_st[tid];
       if (kp.fnorm_out) kp.fnorm_out[b] = s_st[tid] == 2 ? __builtin_nan("") : s_fn[tid];
+    }
+  } else if (kp.mode == MODE_EVAL_FILL) {
+    // the filled LU values of each scenario, block by block (row-major 2x2)
+    const size_t nv = 4 * (size_t)D.nnzb;
+    for (int q = tid; q < 4 * D.nnzb * S; q += nt) {
+      const int blk = q >> 2, b = slice * S + blk % S;
+      if (b < kp.count) kp.out[(size_t)b * nv + 4 * (blk / S) + (q & 3)] = double(c.lu[q]);
     }
   } else if (kp.mode == MODE_EVAL_MISMATCH || kp.mode == MODE_EVAL_STEP) {
     const int nj = D.nj;

@@ -4,6 +4,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <string>
+
+#include "sable_pf.h"
+
 namespace sable {
 
 struct OpParams {
@@ -19,5 +24,19 @@ struct OpParams {
 
 // two launches on st: the per-bus state, then the values
 hipError_t launch_operator_values(const OpParams& p, hipStream_t st);
+
+// the batch-global CSR of the block-diagonal embedding of one scenario's
+// pattern (indptr[rows + 1], indices[nnz], device) for `count` scenarios:
+// crow[count * rows + 1], col[count * nnz] (device, int64)
+hipError_t launch_bde_csr(const int* indptr, const int* indices, int rows, int cols, int nnz, int count,
+                          int64_t* crow, int64_t* col, hipStream_t st);
+
+// launch parameters of operator `which` of a template, except the per-bus
+// state buffer `ef`; validates the arguments and sets the pf_last_error
+// message on failure (PF_OK or a PF_E* code); device: the template's
+int operator_params(pf_template* t, int which, int count, const double* vm, const double* va, double* values,
+                    const char* name, OpParams& p, int& device);
+// message returned by pf_last_error on this thread
+void set_error(const std::string& msg);
 
 }  // namespace sable

@@ -7,6 +7,9 @@
 // forms, once per (scenario, bus), the rectangular voltage e + jf and the
 // calculated injection P + jQ that the diagonal entries need.
 #include "pf_operators.h"
+
+#include <algorithm>
+
 #include "operators.h"
 
 namespace sable {
@@ -105,4 +108,31 @@ hipError_t launch_operator_values(const OpParams& p, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Block-diagonal embedding of one scenario's CSR pattern (eq. BDE_global):
+// scenario b's block sits at row offset b * rows and column offset b * cols,
+// its values at offset b * nnz.  One thread per global row pointer and per
+// global column index.
+__global__ void __launch_bounds__(256) k_bde_csr(const int* indptr, const int* indices, int rows, int cols,
+                                                 int nnz, int count, int64_t* crow, int64_t* col) {
+  const size_t o = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t nr = (size_t)count * rows, nc = (size_t)count * nnz;
+  if (o <= nr) {
+    const size_t b = rows > 0 ? o / rows : 0, r = o - b * rows;
+    crow[o] = (o == nr) ? (int64_t)nc : (int64_t)b * nnz + indptr[r];
+  }
+  if (o < nc) {
+    const size_t b = o / nnz, v = o - b * nnz;
+    col[o] = (int64_t)b * cols + indices[v];
+  }
+}
+
+hipError_t launch_bde_csr(const int* indptr, const int* indices, int rows, int cols, int nnz, int count,
+                          int64_t* crow, int64_t* col, hipStream_t st) {
+  const size_t work = std::max((size_t)count * rows + 1, (size_t)count * nnz);
+  hipLaunchKernelGGL(k_bde_csr, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, st, indptr, indices, rows,
+                     cols, nnz, count, crow, col);
+  return hipGetLastError();
+}
+
 }  // namespace sable
+

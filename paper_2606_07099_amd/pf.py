@@ -12,8 +12,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (PFError, PFOptions, PFStats, check, lib, PF_FP64, PF_MIXED, PF_EVAL_ADJOINT,
-                   PF_EVAL_JACOBIAN, PF_EVAL_MISMATCH, PF_EVAL_STEP, PF_OP_BASE, PF_OP_J1, PF_OP_J1T,
-                   PF_OP_J2T, PF_OP_J3T)
+                   PF_EVAL_FILL, PF_EVAL_JACOBIAN, PF_EVAL_MISMATCH, PF_EVAL_STEP, PF_OP_BASE, PF_OP_J1,
+                   PF_OP_J1T, PF_OP_J2T, PF_OP_J3T)
 
 _I32P = ctypes.POINTER(ctypes.c_int32)
 _F64P = ctypes.POINTER(ctypes.c_double)
@@ -228,6 +228,14 @@ class PFTemplate:
                                                _stream_ptr(stream)))
         return tuple(outs)
 
+    def block_pattern(self):
+        """(row_bus, col_bus) of every 2x2 block of L+U in the library's order."""
+        nnzb = self.info()["nnzb_lu"]
+        rb = np.zeros(nnzb, np.int32)
+        cb = np.zeros(nnzb, np.int32)
+        check(lib().pf_template_block_pattern(self._h, rb.ctypes.data_as(_I32P), cb.ctypes.data_as(_I32P)))
+        return rb, cb
+
     def operator_pattern(self, which):
         """One scenario's CSR pattern of operator ``which`` (see :func:`operator_pattern`)."""
         return operator_pattern(self.n_bus, self._bt, self._ip, self._ix, which)
@@ -246,15 +254,14 @@ class PFTemplate:
             raise ValueError("vm and va must have the same shape [count, n_bus]")
         cache = self.__dict__.setdefault("_op_cache", {})
         key = (int(which), count, vm.device)
-        if key not in cache:
+        if key not in cache:   # the batch-global pattern, expanded by the library
             pat = self.operator_pattern(which)
             nr, nc, nnz = pat["n_rows"], pat["n_cols"], int(pat["indices"].size)
-            ip = torch.as_tensor(pat["indptr"], dtype=torch.int64)
-            ix = torch.as_tensor(pat["indices"], dtype=torch.int64)
-            crow = torch.cat([(ip[:-1].unsqueeze(0) + nnz * torch.arange(count).unsqueeze(1)).reshape(-1),
-                              torch.tensor([nnz * count])]).to(vm.device)
-            col = (ix.unsqueeze(0) + nc * torch.arange(count).unsqueeze(1)).reshape(-1).to(vm.device)
-            cache[key] = (crow, col, nnz, (count * nr, count * nc))
+            crow = torch.empty(count * nr + 1, dtype=torch.int64, device=vm.device)
+            col = torch.empty(max(count * nnz, 1), dtype=torch.int64, device=vm.device)
+            check(lib().pf_operator_bde_csr(self._h, int(which), count, ctypes.c_void_p(crow.data_ptr()),
+                                            ctypes.c_void_p(col.data_ptr()), _stream_ptr(stream)))
+            cache[key] = (crow, col[:count * nnz], nnz, (count * nr, count * nc))
         crow, col, nnz, shape = cache[key]
         if out is not None:
             values = out.values()
@@ -274,7 +281,8 @@ class PFTemplate:
         import torch
         count = self.batch if count is None else int(count)
         nj = self.n_j
-        shape = (count, nj, nj) if mode == PF_EVAL_JACOBIAN else (count, nj)
+        shape = {PF_EVAL_JACOBIAN: (count, nj, nj),
+                 PF_EVAL_FILL: (count, 4 * self.info()["nnzb_lu"])}.get(mode, (count, nj))
         out = torch.empty(shape, dtype=torch.float64, device=vm.device)
         r = ctypes.c_void_p(0)
         if rhs is not None:
@@ -291,5 +299,5 @@ class PFTemplate:
 
 
 __all__ = ["PFTemplate", "ybus_from_branches", "symbolic_analyze", "operator_pattern", "PFError",
-           "PF_EVAL_MISMATCH", "PF_EVAL_JACOBIAN", "PF_EVAL_STEP", "PF_EVAL_ADJOINT", "PF_OP_BASE",
+           "PF_EVAL_MISMATCH", "PF_EVAL_JACOBIAN", "PF_EVAL_STEP", "PF_EVAL_ADJOINT", "PF_EVAL_FILL", "PF_OP_BASE",
            "PF_OP_J1", "PF_OP_J1T", "PF_OP_J2T", "PF_OP_J3T"]

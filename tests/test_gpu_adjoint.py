@@ -27,8 +27,13 @@ def _gpu_grads(tpl, d, device):
 
 
 @pytest.mark.parametrize("name,precision,n_check", [("c0", "fp64", 64), ("c3", "fp64", 8),
-                                                    ("c1", "mixed", 16), ("c3", "mixed", 8)])
+                                                    ("c1", "mixed", 16), ("c3", "mixed", 8),
+                                                    ("c2", "fp64", 6), ("c2", "mixed", 6)])
 def test_adjoint_matches_dense_oracle_gradient(name, precision, n_check, device):
+    """Every grid in the launch configuration of its full batch (the 1354-bus
+    batch of 4096 runs HBM-resident slices of 16 scenarios, whose adjoint
+    reads the forward solve's slice workspace in place), sampled scenarios
+    against the dense oracle."""
     spec, net, sc, tpl, d, tol = make_gpu_case(name, device, precision=precision)
     vm, va, status, (g_pd, g_qd, g_pg, g_vs) = _gpu_grads(tpl, d, device)
     assert np.all(status == 0)
