@@ -317,6 +317,22 @@ int pf_operator_values(pf_template* tpl, int32_t which, int32_t count, const dou
                        const double* va, double* values, void* hip_stream);
 
 /*
+ * pf_operator_values for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, values and errors, but the per-bus voltages and
+ * injections live in a fixed 32 MiB device array that the library holds on
+ * each device it runs on until the process ends, so the call allocates
+ * nothing, not even on its first use.  A batch whose state (32 bytes per bus
+ * and scenario) exceeds the array is processed in consecutive pieces on
+ * hip_stream; a network of more than 2^20 buses is rejected with PF_EINVAL.
+ * All calls on one device share the array: calls that overlap on one device
+ * (different streams or threads) race.  Asynchronous on hip_stream.
+ * Errors: PF_EINVAL, PF_EHIP.
+ */
+int pf_operator_values_static(pf_template* tpl, int32_t which, int32_t count, const double* vm,
+                              const double* va, double* values, void* hip_stream);
+
+/*
  * Row pointers and column indices of the batch-global operator `which` for
  * `count` scenarios: the block-diagonal embedding of one scenario's pattern
  * (eq. BDE_global; scenario b's block at row offset b * n_rows and column

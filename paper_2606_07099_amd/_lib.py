@@ -21,7 +21,8 @@ PF_OP_BASE, PF_OP_J1, PF_OP_J1T, PF_OP_J2T, PF_OP_J3T = 0, 1, 2, 3, 4
 EXPORTED = ("pf_default_options", "pf_last_error", "pf_ybus_from_branches", "pf_template_build",
             "pf_template_info", "pf_template_destroy", "pf_symbolic_analyze", "pf_solve_batch",
             "pf_adjoint_batch", "pf_eval_batch", "pf_recover_batch", "pf_adjoint_completed_batch",
-            "pf_operator_pattern", "pf_operator_values", "pf_operator_bde_csr", "pf_template_block_pattern")
+            "pf_operator_pattern", "pf_operator_values", "pf_operator_bde_csr", "pf_template_block_pattern",
+            "pf_operator_values_static")
 
 
 class PFOptions(ctypes.Structure):

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsablepf.so")
-SOURCES = ["pf_kernels.hip", "pf_operators.hip", "pf_api.cpp", "symbolic.cpp", "operators.cpp"]
+SOURCES = ["pf_kernels.hip", "pf_operators.hip", "pf_operator_static.hip", "pf_api.cpp", "symbolic.cpp",
+           "operators.cpp"]
 ARCH = os.environ.get("SABLE_OFFLOAD_ARCH", "gfx950")
 
 
