@@ -7,15 +7,29 @@ HBM: the plain FP64 Newton solve, the mixed-precision solve (FP32 LU
 refactorisation and solves, FP64 mismatch / convergence / update and two
 FP64-residual refinement steps), one differentiable-layer forward + backward
 (mixed-precision solve keeping the factors + adjoint), the mixed-precision
-solve with adaptive refinement and without refinement, and one layer forward
-+ backward through both completion steps (Step-2 recovery of the generation
-block and its backward term).  Each part is timed with HIP events on the
-stream the kernels run on.
+solve with adaptive refinement and without refinement, one layer forward +
+backward through both completion steps (Step-2 recovery of the generation
+block and its backward term), one training step of the synthetic task and a
+refresh of the exported operators.  Each part is timed with HIP events on
+the stream the kernels run on; rates use the median over the timed steps.
 
 ``value`` is the mixed-precision solves/s; the other rates are reported
 beside it.  The roofline entry covers the dominant kernel (the
 mixed-precision Newton kernel): algorithmic bytes per launch (the model in
-``algorithmic_bytes_per_solve``) over its measured average launch duration.
+``algorithmic_bytes_per_solve``) over its median launch duration.
+
+Legs on the other grids (``--legs``, default all three), each from its own
+templates with 3 warm-up runs and the median of ``--repeats`` timed runs:
+the 1354-bus batch of 4096 (FP64 and mixed-precision solves, the refinement
+variants, and the layer), the 300-bus batch of 2048 (the differentiable
+layer as its workload states it: FP64 template, tolerance 1e-10, forward +
+backward), and the 9241-bus batch of 256 (FP64 and mixed-precision solves,
+mixed-precision forward + FP32-factor adjoint in one autograd step, peak
+device bytes and the LU fill ratio).  Each leg carries its own roofline.
+
+``--phases`` loads the measurement build of the library
+(libsablepf_phases.so) and reports the Newton kernel's per-phase time of
+workgroup 0 on every grid (its timings carry the counters' overhead).
 ``cpu_baseline`` times the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
@@ -32,16 +46,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_amd/csrc/pf_kernels.h")
 
-# HBM bytes per launch of the mixed-precision Newton kernel on the default
-# workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE passes (each scaled by
-# the same counter on a 512 MiB device-to-device copy), keyed by the SHA-256
-# of the kernel sources they were taken on; a changed kernel reports null.
-# Sources: profiles/k_newton_118bus_b1024_hbm_counters.md,
-# profiles/k_newton_1354bus_b4096_hbm_counters.md
-MEASURED_TRAFFIC = {
-    "54aa4290f59904b38a63c93c86efd80e2d2982242dc8796505c573aabb1edc36": {"c1": 6940356,
-                                                                         "c2": 46518049629},
-}
+# HBM bytes per launch of the Newton kernel ("grid/precision" on the full
+# batch), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes (each scaled by the
+# same counter on a 512 MiB device-to-device copy), keyed by the SHA-256 of
+# the kernel sources they were taken on; a changed kernel reports null.
+# Sources: profiles/*_hbm_counters.md
+MEASURED_TRAFFIC = {}
 
 
 def parse():
@@ -49,6 +59,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--legs", default="c2,c3,c4",
+                    help="comma-separated other grids to time after the main workload ('none' for none)")
+    ap.add_argument("--repeats", type=int, default=10, help="timed runs per leg measurement (median)")
+    ap.add_argument("--phases", action="store_true",
+                    help="per-phase clocks of the Newton kernel (measurement build of the library)")
     ap.add_argument("--workload", default="c1", help="grid name in gen.grids.SPECS")
     ap.add_argument("--scenarios", default="lognormal", choices=("lognormal", "uniform10"),
                     help="load scenarios: lognormal scaling of each PQ load, or the paper's "
@@ -124,12 +139,250 @@ def cpu_baseline(name, batch, budget_s, mode="lognormal"):
             "solve_only_value": solve_rate, "wall_s": wall}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def median_seconds(fn, warmup, repeats):
+    """Median duration of fn() over `repeats` timed runs (HIP events on the
+    current stream, where the library enqueues its kernels), after `warmup`
+    untimed ones."""
+    import numpy as np
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    marks = []
+    for _ in range(repeats):
+        a, b = _events(torch)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        marks.append((a, b))
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in marks]) * 1e-3)
+
+
+def roofline_entry(kernel, n_bus, nnz_lu, iters, w, refine, batch, seconds, grid, precision, regime):
+    bytes_launch = batch * algorithmic_bytes_per_solve(n_bus, nnz_lu, iters, w, refine)
+    achieved = bytes_launch / seconds / 1e9
+    traffic = MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(f"{grid}/{precision}")
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_over_algorithmic": (traffic / bytes_launch) if traffic else None,
+            "kernel_source_sha256": kernel_source_hash()[:16], "kernel": kernel,
+            "bytes_per_launch": bytes_launch, "median_launch_ms": 1e3 * seconds,
+            "mean_updates": iters, "regime": regime}
+
+
+def _solve_stats(out):
+    import numpy as np
+    it, st, fn = (x.cpu().numpy() for x in out[2:])
+    return {"iterations": np.bincount(it).tolist(), "converged": int((st == 0).sum()),
+            "max_final_mismatch": float(np.nanmax(fn)), "mean_updates": float(it.mean())}
+
+
+def solve_leg(name, args, scenario_mode="lognormal"):
+    """FP64 and mixed-precision (2, adaptive and no refinement) solves and
+    the layer (forward + adjoint) on the full batch of one grid."""
+    import torch
+    from gen.grids import make_case
+    from paper_2606_07099_amd import PFLayer, PFTemplate
+    spec, net, sc = make_case(name, scenario_mode=scenario_mode)
+    B, dev = sc.batch, torch.device("cuda:0")
+    d = {k: torch.as_tensor(getattr(sc, k), device=dev) for k in ("pd", "qd", "pg", "vset")}
+    res = {"workload": f"{spec.n_bus}-bus synthetic meshed grid, batch {B}, tol {spec.tol:g}",
+           "n_bus": spec.n_bus, "batch": B, "tol": spec.tol}
+    outs = {}
+    variants = (("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed")),
+                ("mixed_adaptive", dict(precision="mixed", refine_adaptive=True)),
+                ("mixed_unrefined", dict(precision="mixed", refine_steps=0)))
+    infos = {}
+    for key, kw in variants:
+        t0 = time.perf_counter()
+        tpl = PFTemplate.from_network(net, B, tol=spec.tol, keep_factors=False, **kw)
+        build_s = time.perf_counter() - t0
+        out = [torch.empty((B, net.n_bus), dtype=torch.float64, device=dev) for _ in range(2)] + \
+            [torch.empty(B, dtype=torch.int32, device=dev) for _ in range(2)] + \
+            [torch.empty(B, dtype=torch.float64, device=dev)]
+        sec = median_seconds(lambda: tpl.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=out),
+                             args.warmup, args.repeats)
+        outs[key] = out
+        infos[key] = tpl.info()
+        res[key] = {"solves_per_s": B / sec, "ms": 1e3 * sec, "template_build_ms": 1e3 * build_s,
+                    **_solve_stats(out)}
+        del tpl
+    # the adaptive variant runs a refinement solve only while the FP64 residual
+    # of the correction is above the forcing term; count what it did
+    res["mixed_adaptive"]["note"] = ("inexact-Newton forcing term; when no refinement solve runs it is "
+                                     "the unrefined (R = 0) iteration")
+    # the layer: mixed-precision template keeping its factors, forward + adjoint
+    tpl = PFTemplate.from_network(net, B, tol=spec.tol, precision="mixed", keep_factors=True)
+    layer = PFLayer(tpl)
+    leaves = {k: d[k].clone().requires_grad_(True) for k in d}
+
+    def step():
+        for v in leaves.values():
+            v.grad = None
+        vm, va = layer(leaves["pd"], leaves["qd"], leaves["pg"], leaves["vset"])
+        L = (torch.relu(vm - 1.05) ** 2).sum() + (torch.relu(0.95 - vm) ** 2).sum() + 0.1 * (va ** 2).sum()
+        L.backward()
+    sec = median_seconds(step, args.warmup, args.repeats)
+    res["layer_mixed"] = {"fwd_bwd_samples_per_s": B / sec, "ms": 1e3 * sec}
+    del layer, tpl
+    res["fp64_over_mixed"] = res["fp64"]["ms"] / res["mixed"]["ms"]
+    info = infos["mixed"]
+    res["template"] = {k: info[k] for k in ("n_j", "nnz_j1", "nnzb_lu", "nnz_lu", "fill_ratio", "n_levels_l",
+                                            "n_levels_u", "lds_resident", "block_threads", "lds_bytes",
+                                            "slice_width", "workspace_bytes")}
+    regime = ("HBM-resident slices of {} scenarios per workgroup: state and factors streamed from HBM"
+              .format(info["slice_width"]) if not info["lds_resident"] else "cache-resident (LDS)")
+    res["roofline"] = {
+        "mixed": roofline_entry("k_newton<float> (mixed precision, 2 refinement steps)", net.n_bus,
+                                info["nnz_lu"], res["mixed"]["mean_updates"], 4, 2, B,
+                                res["mixed"]["ms"] * 1e-3, name, "mixed", regime),
+        "fp64": roofline_entry("k_newton<double> (FP64)", net.n_bus, infos["fp64"]["nnz_lu"],
+                               res["fp64"]["mean_updates"], 8, 0, B, res["fp64"]["ms"] * 1e-3, name, "fp64",
+                               regime)}
+    return res
+
+
+def layer_leg_c3(args):
+    """The differentiable-layer workload as stated for the 300-bus grid:
+    FP64 template, forward Newton to 1e-10, adjoint reusing the factors, the
+    voltage-band + angle loss; fwd+bwd samples/s."""
+    import torch
+    from gen.grids import make_case
+    from paper_2606_07099_amd import PFLayer, PFTemplate
+    spec, net, sc = make_case("c3")
+    B, dev = sc.batch, torch.device("cuda:0")
+    d = {k: torch.as_tensor(getattr(sc, k), device=dev) for k in ("pd", "qd", "pg", "vset")}
+    tpl = PFTemplate.from_network(net, B, tol=spec.tol, precision="fp64", keep_factors=True)
+    layer = PFLayer(tpl)
+    leaves = {k: d[k].clone().requires_grad_(True) for k in d}
+    state = {}
+
+    def step():
+        for v in leaves.values():
+            v.grad = None
+        vm, va = layer(leaves["pd"], leaves["qd"], leaves["pg"], leaves["vset"])
+        L = (torch.relu(vm - 1.05) ** 2).sum() + (torch.relu(0.95 - vm) ** 2).sum() + 0.1 * (va ** 2).sum()
+        L.backward()
+        state["L"] = L
+    sec = median_seconds(step, args.warmup, args.repeats)
+    out = [torch.empty((B, net.n_bus), dtype=torch.float64, device=dev) for _ in range(2)] + \
+        [torch.empty(B, dtype=torch.int32, device=dev) for _ in range(2)] + \
+        [torch.empty(B, dtype=torch.float64, device=dev)]
+    sec_fwd = median_seconds(lambda: tpl.solve(d["pd"], d["qd"], d["pg"], d["vset"], out=out),
+                             args.warmup, args.repeats)
+    info = tpl.info()
+    return {"workload": f"{spec.n_bus}-bus synthetic meshed grid, batch {B}, FP64, forward to {spec.tol:g}, "
+                        "adjoint reusing the factors at the solution",
+            "fwd_bwd_samples_per_s": B / sec, "fwd_bwd_ms": 1e3 * sec,
+            "forward_with_refactor_solves_per_s": B / sec_fwd, "forward_ms": 1e3 * sec_fwd,
+            "loss": float(state["L"]), **_solve_stats(out),
+            "template": {k: info[k] for k in ("nnz_lu", "fill_ratio", "lds_resident", "slice_width",
+                                              "workspace_bytes")}}
+
+
+def layer_leg_c4(args):
+    """The 9241-bus batch of 256: mixed-precision forward + FP32-factor
+    adjoint in one autograd step (with the configured 2 FP64-residual
+    refinement steps, and without refinement as the paper runs it), peak
+    device bytes and the LU fill ratio."""
+    import torch
+    from gen.grids import make_case
+    from paper_2606_07099_amd import PFLayer, PFTemplate
+    spec, net, sc = make_case("c4")
+    B, dev = sc.batch, torch.device("cuda:0")
+    d = {k: torch.as_tensor(getattr(sc, k), device=dev) for k in ("pd", "qd", "pg", "vset")}
+    res = {}
+    for key, refine in (("mixed", 2), ("mixed_unrefined", 0)):
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        tpl = PFTemplate.from_network(net, B, tol=spec.tol, precision="mixed", refine_steps=refine,
+                                      keep_factors=True)
+        layer = PFLayer(tpl)
+        leaves = {k: d[k].clone().requires_grad_(True) for k in d}
+
+        def step():
+            for v in leaves.values():
+                v.grad = None
+            vm, va = layer(leaves["pd"], leaves["qd"], leaves["pg"], leaves["vset"])
+            L = (torch.relu(vm - 1.05) ** 2).sum() + (torch.relu(0.95 - vm) ** 2).sum() + 0.1 * (va ** 2).sum()
+            L.backward()
+        sec = median_seconds(step, args.warmup, args.repeats)
+        info = tpl.info()
+        res[key] = {"fwd_bwd_samples_per_s": B / sec, "fwd_bwd_ms": 1e3 * sec, "refine_steps": refine,
+                    "peak_device_bytes": int(info["workspace_bytes"] + torch.cuda.max_memory_allocated()),
+                    "template_workspace_bytes": int(info["workspace_bytes"]),
+                    "fill_ratio": info["fill_ratio"], "nnz_lu": info["nnz_lu"], "nnz_j1": info["nnz_j1"]}
+        del layer, tpl, leaves
+    return res
+
+
+PHASE_NAMES = ("setup", "mismatch", "fill", "factor_levels", "factor_tail", "bsolve_tail", "bsolve_levels",
+               "refine_dv", "refine_residual", "refine_fsolve_levels", "refine_tail", "refine_bsolve_levels",
+               "other", "keep_refactor", "output")
+
+
+def phase_report(grids, args):
+    """Per-launch time of each Newton phase (workgroup 0, wall clock), FP64
+    and mixed precision (2 refinement steps), on each grid's full batch."""
+    import ctypes
+    import numpy as np
+    import torch
+    from gen.grids import make_case
+    from paper_2606_07099_amd import PFTemplate
+    from paper_2606_07099_amd._lib import check, lib
+    L = lib()
+    buf = (ctypes.c_uint64 * 32)()
+    rate = ctypes.c_double(0.0)
+    out = {}
+    for name in grids:
+        spec, net, sc = make_case(name)
+        B, dev = sc.batch, torch.device("cuda:0")
+        d = {k: torch.as_tensor(getattr(sc, k), device=dev) for k in ("pd", "qd", "pg", "vset")}
+        out[name] = {}
+        for prec in ("fp64", "mixed"):
+            tpl = PFTemplate.from_network(net, B, tol=spec.tol, precision=prec, keep_factors=False)
+            for _ in range(args.warmup):
+                tpl.solve(d["pd"], d["qd"], d["pg"], d["vset"])
+            check(L.pf_debug_phase_clocks(buf, 32, 1, ctypes.byref(rate)))
+            for _ in range(args.repeats):
+                tpl.solve(d["pd"], d["qd"], d["pg"], d["vset"])
+            check(L.pf_debug_phase_clocks(buf, 32, 1, ctypes.byref(rate)))
+            t = np.array(buf[:32], dtype=np.float64)
+            launches = max(t[16], 1.0)
+            us = 1e6 * t[:15] / rate.value / launches
+            out[name][prec] = {"us_per_launch": {k: float(v) for k, v in zip(PHASE_NAMES, us)},
+                               "total_us": float(us.sum()), "newton_steps_per_launch": float(t[17] / launches),
+                               "refine_steps_per_launch": float(t[18] / launches),
+                               "slice_width": tpl.info()["slice_width"]}
+            del tpl
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported "
                                    "(scenarios are independent and would shard across GPUs with no exchange)"}))
         sys.exit(2)
+    if args.phases:
+        os.environ["SABLE_PHASE_CLOCKS"] = "1"   # before the library is loaded
     import numpy as np
     import torch
     from gen.grids import SPECS, make_case
@@ -241,24 +494,24 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    t64 = np.array([m[0].elapsed_time(m[1]) for m in marks]) * 1e-3
-    tmp = np.array([m[1].elapsed_time(m[2]) for m in marks]) * 1e-3
-    tfb = np.array([m[2].elapsed_time(m[3]) for m in marks]) * 1e-3
-    tad = np.array([m[3].elapsed_time(m[4]) for m in marks]) * 1e-3
-    tr0 = np.array([m[4].elapsed_time(m[5]) for m in marks]) * 1e-3
-    tfc = np.array([m[5].elapsed_time(m[6]) for m in marks]) * 1e-3
-    ttr = np.array([m[6].elapsed_time(m[7]) for m in marks]) * 1e-3
-    top = np.array([m[7].elapsed_time(m[8]) for m in marks]) * 1e-3
+    def med(k):
+        return float(np.median([m[k].elapsed_time(m[k + 1]) for m in marks]) * 1e-3)
+    t64, tmp, tfb, tad, tr0, tfc, ttr, top = (med(k) for k in range(8))
     op_nnz = {int(w): int(op_mats[w].values().numel()) for w in op_ids}
     train_losses = [float(x) for x in train_losses]
-    itad, stad, fnad = (x.cpu().numpy() for x in outad[2:])
-    itr0, str0, fnr0 = (x.cpu().numpy() for x in outr0[2:])
-    it64, st64, fn64 = (x.cpu().numpy() for x in out64[2:])
-    itmp, stmp, fnmp = (x.cpu().numpy() for x in outmp[2:])
-    mp_rate = B / tmp.mean()
-    # dominant kernel: the mixed-precision Newton kernel, one launch per solve
-    bytes_launch = B * algorithmic_bytes_per_solve(net.n_bus, infomp["nnz_lu"], float(itmp.mean()), 4, 2)
-    achieved = bytes_launch / tmp.mean() / 1e9
+    st = {k: _solve_stats(o) for k, o in (("fp64", out64), ("mixed", outmp), ("mixed_adaptive", outad),
+                                          ("mixed_unrefined", outr0))}
+    mp_rate = B / tmp
+    cache_regime = ("cache-resident: state, factors and schedules live in LDS (the HBM counters read "
+                    "6.9 MB per launch, the boundary I/O, against the streaming model's bytes), and the "
+                    "SQ counters show the launch waiting on LDS results and barriers; frac is the "
+                    "streaming model over the HBM peak, not an HBM efficiency"
+                    if infomp["lds_resident"] else "HBM-resident slices")
+    roof = roofline_entry("k_newton<float> (mixed-precision Newton, one launch per solve)", net.n_bus,
+                          infomp["nnz_lu"], st["mixed"]["mean_updates"], 4, 2, B, tmp, name, "mixed",
+                          cache_regime)
+    if not (B == SPECS[name].batch and args.scenarios == "lognormal"):
+        roof["traffic"] = roof["traffic_over_algorithmic"] = None
 
     res = {
         "metric": "PF solves/sec (FP32-LU+refine vs FP64) & PF-layer fwd+bwd samples/sec @1e-8pu",
@@ -278,16 +531,18 @@ def main():
                    "n_bus": spec.n_bus, "n_pv": spec.n_pv, "n_branch": spec.n_branch,
                    "batch": B, "tol": spec.tol, "refine_steps": 2, "scenarios": args.scenarios,
                    "parallelism": "single GPU"},
-        "fp64_solves_per_s": B / t64.mean(),
+        "timing": f"median over {args.steps} steps of HIP events on the kernels' stream, after {args.warmup} "
+                  "warm-up steps",
+        "fp64_solves_per_s": B / t64,
         "mixed_solves_per_s": mp_rate,
-        "layer_fwd_bwd_samples_per_s": B / tfb.mean(),
-        "mixed_adaptive_solves_per_s": B / tad.mean(),
-        "mixed_unrefined_solves_per_s": B / tr0.mean(),
-        "layer_completed_fwd_bwd_samples_per_s": B / tfc.mean(),
-        "train_samples_per_s": B / ttr.mean(),
+        "layer_fwd_bwd_samples_per_s": B / tfb,
+        "mixed_adaptive_solves_per_s": B / tad,
+        "mixed_unrefined_solves_per_s": B / tr0,
+        "layer_completed_fwd_bwd_samples_per_s": B / tfc,
+        "train_samples_per_s": B / ttr,
         "operator_refresh": {"operators": "J1, J1^T, J2^T, J3^T (batch-global CSR, values in place)",
-                             "values": sum(op_nnz.values()), "ms": 1e3 * top.mean(),
-                             "values_per_s": sum(op_nnz.values()) / top.mean()},
+                             "values": sum(op_nnz.values()), "ms": 1e3 * top,
+                             "values_per_s": sum(op_nnz.values()) / top},
         "train": {"task": "MLP (2 x 256 hidden) -> PV dispatch and |V| setpoints -> PF layer (both "
                           "completion steps, mixed precision) -> generation cost + voltage and "
                           "reactive penalties -> Adam",
@@ -295,18 +550,13 @@ def main():
                   "optimizer_steps": len(train_losses),
                   "peak_torch_bytes": int(torch.cuda.max_memory_allocated()),
                   "template_workspace_bytes": int(task.tpl.info()["workspace_bytes"])},
-        "ms": {"fp64_solve": 1e3 * t64.mean(), "mixed_solve": 1e3 * tmp.mean(),
-               "mixed_adaptive_solve": 1e3 * tad.mean(), "mixed_unrefined_solve": 1e3 * tr0.mean(),
-               "layer_fwd_bwd": 1e3 * tfb.mean(), "layer_completed_fwd_bwd": 1e3 * tfc.mean(),
-               "train_step": 1e3 * ttr.mean(),
-               "template_build": 1e3 * t_build},
-        "iterations": {"fp64": np.bincount(it64).tolist(), "mixed": np.bincount(itmp).tolist(),
-                       "mixed_adaptive": np.bincount(itad).tolist(),
-                       "mixed_unrefined": np.bincount(itr0).tolist()},
-        "converged": {"fp64": int((st64 == 0).sum()), "mixed": int((stmp == 0).sum()),
-                      "mixed_adaptive": int((stad == 0).sum()), "mixed_unrefined": int((str0 == 0).sum())},
-        "max_final_mismatch": {"fp64": float(fn64.max()), "mixed": float(fnmp.max()),
-                               "mixed_adaptive": float(fnad.max()), "mixed_unrefined": float(fnr0.max())},
+        "ms": {"fp64_solve": 1e3 * t64, "mixed_solve": 1e3 * tmp,
+               "mixed_adaptive_solve": 1e3 * tad, "mixed_unrefined_solve": 1e3 * tr0,
+               "layer_fwd_bwd": 1e3 * tfb, "layer_completed_fwd_bwd": 1e3 * tfc,
+               "train_step": 1e3 * ttr, "template_build": 1e3 * t_build},
+        "iterations": {k: v["iterations"] for k, v in st.items()},
+        "converged": {k: v["converged"] for k, v in st.items()},
+        "max_final_mismatch": {k: v["max_final_mismatch"] for k, v in st.items()},
         "device_memory": {"templates_workspace_bytes": int(sum(t.info()["workspace_bytes"] for t in
                                                               (tpl64, tplmp, tpllay, tplad, tplr0, task.tpl))),
                           "torch_peak_bytes": int(torch.cuda.max_memory_allocated()),
@@ -316,16 +566,27 @@ def main():
         "template": {k: infomp[k] for k in ("n_j", "nnz_j1", "nnzb_lu", "nnz_lu", "fill_ratio",
                                             "n_levels_l", "n_levels_u", "lds_resident",
                                             "block_threads", "lds_bytes", "slice_width", "workspace_bytes")},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(name)
-                                 if B == SPECS[name].batch and args.scenarios == "lognormal" else None),
-                     "kernel_source_sha256": kernel_source_hash()[:16],
-                     "kernel": "k_newton<float> (mixed-precision Newton, one launch per solve)",
-                     "bytes_per_launch": bytes_launch, "avg_launch_ms": 1e3 * tmp.mean()},
+        "roofline": roof,
+        "phase_clocks_build": bool(args.phases),
     }
+    del tpl64, tplmp, tpllay, tplad, tplr0, layer, layerc, task, op_mats
+    torch.cuda.empty_cache()
+    legs = [g for g in args.legs.split(",") if g and g != "none" and g != name]
+    if legs:
+        res["legs"] = {}
+    for g in legs:
+        if g == "c3":
+            res["legs"]["c3_layer"] = layer_leg_c3(args)
+        else:
+            res["legs"][g] = solve_leg(g, args)
+            if g == "c4":
+                res["legs"][g]["layer_fwd_bwd"] = layer_leg_c4(args)
+        torch.cuda.empty_cache()
+    if args.phases:
+        res["phases"] = phase_report([name] + [g for g in legs], args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(name, B, args.cpu_seconds, args.scenarios)
+        res["cpu_baseline"]["cpu_model"] = cpu_model()
     print(json.dumps(res), flush=True)
 
 

@@ -380,6 +380,22 @@ int pf_eval_batch(pf_template* tpl, int32_t mode, int32_t count, const double* p
                   const double* qd, const double* pg, const double* vset, const double* vm,
                   const double* va, const double* rhs, double* out, void* hip_stream);
 
+/*
+ * Measurement aid: per-phase wall-clock counters of the Newton kernel,
+ * present only in the library variant built with -DSABLE_PHASE_CLOCKS
+ * (libsablepf_phases.so); the production library returns PF_EINVAL.
+ * Workgroup 0 of every Newton launch adds the ticks of the constant-rate wall
+ * clock spent in each phase (slots 0..14: set-up, mismatch, fill, factor
+ * levels, factor tail, backward tail, backward levels, refinement dV,
+ * refinement residual, refinement forward levels, refinement tail,
+ * refinement backward levels, other, kept-factor refresh, outputs) and event
+ * counts (slot 16: launches, 17: Newton corrections, 18: refinement steps).
+ * Copies the first n slots to the host array ticks[n] after a device
+ * synchronisation, clears them when reset != 0, and writes the clock rate
+ * to *ticks_per_second when not NULL.  Errors: PF_EINVAL, PF_EHIP.
+ */
+int pf_debug_phase_clocks(uint64_t* ticks, int32_t n, int32_t reset, double* ticks_per_second);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsablepf.so")
+# SABLE_PHASE_CLOCKS=1 selects the measurement build with per-phase clocks
+LIB_PATH = os.path.join(HERE, "libsablepf_phases.so" if os.environ.get("SABLE_PHASE_CLOCKS") == "1"
+                        else "libsablepf.so")
 
 PF_OK, PF_EINVAL, PF_ETOPOLOGY, PF_ENOMEM, PF_EHIP, PF_ESTATE = 0, -1, -2, -3, -4, -5
 PF_BUS_PQ, PF_BUS_PV, PF_BUS_SLACK = 0, 1, 2
@@ -22,7 +24,7 @@ EXPORTED = ("pf_default_options", "pf_last_error", "pf_ybus_from_branches", "pf_
             "pf_template_info", "pf_template_destroy", "pf_symbolic_analyze", "pf_solve_batch",
             "pf_adjoint_batch", "pf_eval_batch", "pf_recover_batch", "pf_adjoint_completed_batch",
             "pf_operator_pattern", "pf_operator_values", "pf_operator_bde_csr", "pf_template_block_pattern",
-            "pf_operator_values_static")
+            "pf_operator_values_static", "pf_debug_phase_clocks")
 
 
 class PFOptions(ctypes.Structure):
@@ -86,6 +88,8 @@ def lib():
     L.pf_eval_batch.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.pf_operator_bde_csr.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]
     L.pf_template_block_pattern.argtypes = [_P, _I32P, _I32P]
+    L.pf_debug_phase_clocks.argtypes = [ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTED[2:]:
         getattr(L, name).restype = ctypes.c_int
     _lib = L

@@ -26,20 +26,43 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
-           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+LIB_PHASES = os.path.join(HERE, "libsablepf_phases.so")
+OBJ_DIR = os.path.join(HERE, "_build")
+
+
+def _flags():
+    return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed")
-    os.replace(tmp, LIB)
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles every source (in parallel) and links two libraries: the
+    production one and the measurement variant whose Newton kernel carries
+    per-phase wall-clock counters (-DSABLE_PHASE_CLOCKS)."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    jobs = [(src, os.path.join(OBJ_DIR, os.path.splitext(src)[0] + ".o"), []) for src in SOURCES]
+    jobs.append(("pf_kernels.hip", os.path.join(OBJ_DIR, "pf_kernels_phases.o"), ["-DSABLE_PHASE_CLOCKS"]))
+    cmds = [[hipcc(), *_flags(), *extra, "-c", os.path.join(CSRC, src), "-o", obj] for src, obj, extra in jobs]
+    workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    objs = [obj for _, obj, extra in jobs if not extra]
+    phase_objs = [o if not o.endswith(os.sep + "pf_kernels.o") else jobs[-1][1] for o in objs]
+    for out, ob in ((LIB, objs), (LIB_PHASES, phase_objs)):
+        tmp = out + ".tmp"
+        _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *ob, "-o", tmp], verbose)
+        os.replace(tmp, out)
     build_abi_check(verbose)
     return LIB
 

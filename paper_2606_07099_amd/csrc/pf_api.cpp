@@ -771,6 +771,25 @@ int pf_operator_bde_csr(pf_template* t, int32_t which, int32_t count, int64_t* c
   return PF_OK;
 }
 
+int pf_debug_phase_clocks(uint64_t* ticks, int32_t n, int32_t reset, double* ticks_per_second) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && !ticks)) return fail(PF_EINVAL, "pf_debug_phase_clocks: bad buffer");
+  std::vector<unsigned long long> buf(std::max(n, 1), 0ull);
+  hipError_t he = sable::read_phase_clocks(buf.data(), n, reset != 0);
+  if (he == hipErrorNotSupported)
+    return fail(PF_EINVAL, "pf_debug_phase_clocks: library built without per-phase clocks");
+  if (he != hipSuccess) return hip_fail(he, "pf_debug_phase_clocks");
+  for (int32_t i = 0; i < n; ++i) ticks[i] = buf[i];
+  if (ticks_per_second) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+      return fail(PF_EHIP, "pf_debug_phase_clocks: wall-clock rate query");
+    *ticks_per_second = 1e3 * (double)khz;
+  }
+  return PF_OK;
+}
+
 int pf_template_block_pattern(const pf_template* t, int32_t* row_bus, int32_t* col_bus) {
   g_err.clear();
   if (!t || !row_bus || !col_bus) return fail(PF_EINVAL, "pf_template_block_pattern: NULL argument");

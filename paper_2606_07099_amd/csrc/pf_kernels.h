@@ -18,6 +18,31 @@ enum Mode : int {
   MODE_EVAL_FILL = 5,      // the Jacobian values in the LU positions, before factorisation
 };
 
+// slots of the per-phase wall-clock counters (builds with
+// -DSABLE_PHASE_CLOCKS): ticks of the Newton kernel's phases, then event
+// counts; accumulated over launches by workgroup 0
+enum PhaseSlot : int {
+  PH_SETUP = 0,                // inputs, flat start
+  PH_MISMATCH = 1,             // I = Y V, F1, norms and the convergence test
+  PH_FILL = 2,                 // Jacobian values into the LU positions (Algorithm 1)
+  PH_FACTOR_LEVELS = 3,        // level-scheduled factorisation with the fused forward solve
+  PH_FACTOR_TAIL = 4,          // dense tail factorisation (+ its forward solve)
+  PH_BSOLVE_TAIL = 5,          // backward solve of the tail rows
+  PH_BSOLVE_LEVELS = 6,        // level-scheduled backward solve
+  PH_REFINE_DV = 7,            // refinement: dV from the correction
+  PH_REFINE_RESIDUAL = 8,      // refinement: FP64 residual through Y_bus
+  PH_REFINE_FSOLVE_LEVELS = 9, // refinement: level-scheduled forward solve
+  PH_REFINE_TAIL = 10,         // refinement: tail forward + backward solves
+  PH_REFINE_BSOLVE_LEVELS = 11,// refinement: level-scheduled backward solve
+  PH_OTHER = 12,               // copies of the correction, state update, e + jf
+  PH_KEEP = 13,                // refresh and refactorisation at the solution (kept factors)
+  PH_OUTPUT = 14,              // outputs
+  PH_NEWTON_LAUNCHES = 16,     // count: launches
+  PH_NEWTON_STEPS = 17,        // count: Newton corrections of workgroup 0
+  PH_REFINE_STEPS = 18,        // count: refinement steps of workgroup 0
+  kPhaseSlots = 32
+};
+
 // LDS scratch at the start of every kernel's dynamic LDS: per-(wave,
 // scenario) partial maxima and flags, per-scenario reductions, zero-pivot
 // flags and Newton bookkeeping (iterations, status, final mismatch).
@@ -120,5 +145,8 @@ hipError_t launch_jacobian_dense(const KParams& kp, int grid, hipStream_t st);
 // Step-2 recovery of the generation block for kp.count scenarios
 hipError_t launch_recover(const KParams& kp, hipStream_t st);
 hipError_t set_lds_limits(size_t max_lds);
+// copies (and optionally clears) the per-phase counters; hipErrorNotSupported
+// when the library was built without them
+hipError_t read_phase_clocks(unsigned long long* ticks, int n, bool reset);
 
 }  // namespace sable

@@ -24,6 +24,40 @@
 namespace sable {
 
 // ----------------------------------------------------------------------------
+// per-phase wall-clock accounting, compiled in with -DSABLE_PHASE_CLOCKS:
+// thread 0 of workgroup 0 adds the ticks of the constant-rate wall clock
+// between consecutive phase marks to one counter per phase (every mark
+// follows a workgroup barrier, so the interval is the workgroup's time in
+// that phase).  Without the flag the marks compile to nothing.
+
+#ifdef SABLE_PHASE_CLOCKS
+__device__ unsigned long long g_phase_ticks[kPhaseSlots];
+struct PhaseClock {
+  bool on;
+  unsigned long long t0;
+  __device__ __forceinline__ explicit PhaseClock(int tid) : on(tid == 0 && blockIdx.x == 0), t0(0) {
+    if (on) t0 = wall_clock64();
+  }
+  __device__ __forceinline__ void mark(int ph) {
+    if (on) {
+      const unsigned long long t = wall_clock64();
+      g_phase_ticks[ph] += t - t0;
+      t0 = t;
+    }
+  }
+  __device__ __forceinline__ void count(int slot) {
+    if (on) g_phase_ticks[slot] += 1;
+  }
+};
+#else
+struct PhaseClock {
+  __device__ __forceinline__ explicit PhaseClock(int) {}
+  __device__ __forceinline__ void mark(int) {}
+  __device__ __forceinline__ void count(int) {}
+};
+#endif
+
+// ----------------------------------------------------------------------------
 // small helpers
 
 template <typename T>
@@ -1009,6 +1043,7 @@ template <typename T, bool RES, int S>
 __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton(KParams kp) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, nt = blockDim.x;
+  PhaseClock pc(tid);
   const int slice = blockIdx.x;
   const Dims& D = kp.dims;
   unsigned char* scr = smem;
@@ -1036,6 +1071,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
                          reinterpret_cast<T*>(kp.wsl_t) + (size_t)slice * S * kp.lay.st, kp.lay);
   }
   if (tid < S) { piv[tid] = 0; s_it[tid] = 0; s_st[tid] = 0; s_fn[tid] = 0.0; }
+  pc.count(PH_NEWTON_LAUNCHES);
 
   const int n = D.n_bus, nb = D.nb;
   int act = 0;   // scenarios of the slice still iterating (identical in every thread)
@@ -1078,8 +1114,10 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
   T* td = tl + (size_t)kp.dims.tail_nblk * S * 4;
   T* ty = td + (size_t)kp.dims.tail_t * S * 4;
   TailRow<T> R;                             // this wavefront's factored tail rows
+  pc.mark(PH_SETUP);
   while (true) {
     phase_mismatch<T, S>(m, D, c, tid, nt, scr);
+    pc.mark(PH_MISMATCH);
     for (int s = 0; s < S; ++s) {
       if (!((act >> s) & 1)) continue;
       const double f = fnr[s];
@@ -1101,7 +1139,10 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
     if (!act) break;
     for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
     phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
+    pc.mark(PH_FILL);
+    pc.count(PH_NEWTON_STEPS);
     phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, true, piv, stg);
+    pc.mark(PH_FACTOR_LEVELS);
     if constexpr (RES) {
       if (wv < S) rt_factor<T, S>(m, D, c, wv, ln, true, piv, R);
     } else {
@@ -1110,6 +1151,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       ltail_factor<T, S>(m, D, c, tl, td, ty, tid, nt, true, piv);
     }
     __syncthreads();
+    pc.mark(PH_FACTOR_TAIL);
     for (int s = 0; s < S; ++s)
       if (((act >> s) & 1) && piv[s]) {
         act &= ~(1 << s);
@@ -1122,14 +1164,19 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt);
     }
     __syncthreads();
+    pc.mark(PH_BSOLVE_TAIL);
     phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg);
+    pc.mark(PH_BSOLVE_LEVELS);
     for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
     __syncthreads();
     if (mixed) {
       int ref = act;   // scenarios still refining their correction
       for (int r = 0; r < kp.refine; ++r) {
+        pc.mark(PH_OTHER);
         phase_dv<T, S>(m, D, c, tid, nt);
+        pc.mark(PH_REFINE_DV);
         phase_residual<T, S>(m, D, c, tid, nt, kp.adaptive, scr);
+        pc.mark(PH_REFINE_RESIDUAL);
         if (kp.adaptive) {
           // inexact-Newton forcing term: refine while the FP64 residual of the
           // correction exceeds max(min(0.1, |F|) |F|, 0.1 tol)
@@ -1140,7 +1187,9 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
           }
           if (!ref) break;
         }
+        pc.count(PH_REFINE_STEPS);
         phase_solve<T, S, RES, true>(m, D, c, tid, nt, gmin, stg);
+        pc.mark(PH_REFINE_FSOLVE_LEVELS);
         if constexpr (RES) {
           if (wv < S) {
             rt_fsolve<T, S>(m, D, c, wv, ln, R);
@@ -1152,7 +1201,9 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
           ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt);
         }
         __syncthreads();
+        pc.mark(PH_REFINE_TAIL);
         phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg);
+        pc.mark(PH_REFINE_BSOLVE_LEVELS);
         for (int q = tid; q < 2 * nb * S; q += nt)
           if ((ref >> ((q >> 1) % S)) & 1) c.dx[q] += double(c.y[q]);
         __syncthreads();
@@ -1171,8 +1222,10 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
     __syncthreads();
     phase_set_state<T, S>(D, c, tid, nt, act);
     if (tid < S && ((act >> tid) & 1)) s_it[tid]++;
+    pc.mark(PH_OTHER);
   }
   __syncthreads();
+  pc.mark(PH_OTHER);
 
   // outputs
   if (kp.mode == MODE_SOLVE) {
@@ -1235,6 +1288,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
     }
     __syncthreads();
     if (tid < S && s_st[tid] == 0 && piv[tid]) s_st[tid] = 3;
+    pc.mark(PH_KEEP);
     // LDS-resident slices: the kept state and factors go to the per-scenario
     // workspace, which the adjoint copies into its own LDS slices; the
     // HBM-resident adjoint reads this slice workspace in place
@@ -1261,6 +1315,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
     gi[0] = keep ? s_st[tid] : -1;
     gi[1] = s_it[tid];
   }
+  pc.mark(PH_OUTPUT);
 }
 
 // direct Step-2 terms of the gradients: z2 carries the load of its own row
@@ -1817,6 +1872,23 @@ static hipError_t set_lds_t(int max_lds) {
   set(reinterpret_cast<const void*>(&k_adjoint_slice<T, false, 8>));
   set(reinterpret_cast<const void*>(&k_adjoint_slice<T, false, 16>));
   return e;
+}
+
+hipError_t read_phase_clocks(unsigned long long* ticks, int n, bool reset) {
+#ifdef SABLE_PHASE_CLOCKS
+  if (n > kPhaseSlots) n = kPhaseSlots;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess && n > 0) e = hipMemcpyFromSymbol(ticks, HIP_SYMBOL(g_phase_ticks), n * sizeof(unsigned long long));
+  if (e == hipSuccess && reset) {
+    unsigned long long zero[kPhaseSlots] = {};
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_phase_ticks), zero, sizeof(zero));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
+  return e;
+#else
+  (void)ticks; (void)n; (void)reset;
+  return hipErrorNotSupported;
+#endif
 }
 
 hipError_t set_lds_limits(size_t max_lds) {
