@@ -51,7 +51,18 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # same counter on a 512 MiB device-to-device copy), keyed by the SHA-256 of
 # the kernel sources they were taken on; a changed kernel reports null.
 # Sources: profiles/*_hbm_counters.md
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    "d827ae71c357a811878c0f81165bdf583634bd5a0e3bc74519e0dcb990ef2580": {
+        "c1/mixed": 7017145,
+        "c1/fp64": 7977664,
+        "c2/mixed": 46947579022,
+        "c2/fp64": 49097088470,
+        "c3/mixed": 3747991460,
+        "c3/fp64": 4075729938,
+        "c4/mixed": 67151399410,
+        "c4/fp64": 56105196813,
+    },
+}
 
 
 def parse():
@@ -62,6 +73,9 @@ def parse():
     ap.add_argument("--legs", default="c2,c3,c4",
                     help="comma-separated other grids to time after the main workload ('none' for none)")
     ap.add_argument("--repeats", type=int, default=10, help="timed runs per leg measurement (median)")
+    ap.add_argument("--profile-solve", choices=("fp64", "mixed"), default=None,
+                    help="only time this solve of the workload (one template, --steps launches after "
+                         "--warmup), for profilers that attribute counters per kernel dispatch")
     ap.add_argument("--phases", action="store_true",
                     help="per-phase clocks of the Newton kernel (measurement build of the library)")
     ap.add_argument("--workload", default="c1", help="grid name in gen.grids.SPECS")
@@ -375,6 +389,27 @@ def phase_report(grids, args):
     return out
 
 
+def profile_solve(args, name, spec, net, sc, d):
+    """One solve variant of the workload, nothing else on the device: the
+    known-size copy (if asked), then --warmup and --steps launches."""
+    import torch
+    from paper_2606_07099_amd import PFTemplate
+    B = sc.batch
+    tpl = PFTemplate.from_network(net, B, tol=spec.tol, precision=args.profile_solve, keep_factors=False)
+    if args.copy_reference_mib:
+        src = torch.ones(args.copy_reference_mib << 17, dtype=torch.float64, device="cuda:0")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        del src
+    sec = median_seconds(lambda: tpl.solve(d["pd"], d["qd"], d["pg"], d["vset"]), args.warmup, args.steps)
+    out = tpl.solve(d["pd"], d["qd"], d["pg"], d["vset"])
+    info = tpl.info()
+    print(json.dumps({"workload": f"{spec.n_bus}-bus synthetic meshed grid, batch {B}, tol {spec.tol:g}",
+                      "solve": args.profile_solve, "median_ms": 1e3 * sec, "solves_per_s": B / sec,
+                      "nnz_lu": info["nnz_lu"], "slice_width": info["slice_width"],
+                      **_solve_stats(out)}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -394,6 +429,9 @@ def main():
     B = sc.batch
     dev = torch.device("cuda:0")
     d = {k: torch.as_tensor(getattr(sc, k), device=dev) for k in ("pd", "qd", "pg", "vset")}
+    if args.profile_solve:
+        profile_solve(args, name, spec, net, sc, d)
+        return
     t_build = time.perf_counter()
     tpl64 = PFTemplate.from_network(net, B, tol=spec.tol, precision="fp64", keep_factors=False)
     t_build = time.perf_counter() - t_build
@@ -503,7 +541,7 @@ def main():
                                           ("mixed_unrefined", outr0))}
     mp_rate = B / tmp
     cache_regime = ("cache-resident: state, factors and schedules live in LDS (the HBM counters read "
-                    "6.9 MB per launch, the boundary I/O, against the streaming model's bytes), and the "
+                    "7.0 MB per launch, the boundary I/O, against the streaming model's bytes), and the "
                     "SQ counters show the launch waiting on LDS results and barriers; frac is the "
                     "streaming model over the HBM peak, not an HBM efficiency"
                     if infomp["lds_resident"] else "HBM-resident slices")

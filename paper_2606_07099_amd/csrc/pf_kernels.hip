@@ -309,36 +309,108 @@ __device__ __forceinline__ void block_max(double v, int bad, unsigned char* scr,
 // ----------------------------------------------------------------------------
 // phases (each ends with a workgroup barrier)
 
+// The bus-indexed passes (mismatch, refinement dV and residual) give each
+// thread two items (bus, scenario) at a time, nt apart (so both belong to the
+// same scenario), and issue each item's own loads before its Y_bus row
+// product: with the state in HBM every load is a round trip, and a loop that
+// waits for one row entry at a time leaves the memory system idle.
+
+// Y_bus row products I = sum_q Y_iq (xr + j xi)_j of two items at once: four
+// entries of each row per round, every index, admittance and gathered value
+// of the round loaded before the arithmetic.  Entries past a row's end load
+// bus 0 (in bounds) and are not added; each row is summed in column order.
+template <int S, int U, int W>
+__device__ __forceinline__ void yrow_multi(const Sym& m, const double* xr, const double* xi, const int (&i)[U],
+                                           int s, const bool (&v)[U], double (&ar)[U], double (&ai)[U]) {
+  int q[U], q1[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    q[u] = v[u] ? m.y_rp[i[u]] : 0;
+    q1[u] = v[u] ? m.y_rp[i[u] + 1] : 0;
+    ar[u] = 0.0;
+    ai[u] = 0.0;
+  }
+  while (true) {
+    bool more = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u) more |= q[u] < q1[u];
+    if (!more) break;
+    int j[U][W];
+    double g[U][W], b[U][W], x[U][W], y[U][W];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const bool in = q[u] + w < q1[u];
+        j[u][w] = in ? m.y_ci[q[u] + w] : 0;
+        g[u][w] = in ? m.y_g[q[u] + w] : 0.0;
+        b[u][w] = in ? m.y_b[q[u] + w] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        x[u][w] = xr[sI<S>(j[u][w], s)];
+        y[u][w] = xi[sI<S>(j[u][w], s)];
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        if (q[u] + w < q1[u]) {
+          ar[u] += g[u][w] * x[u][w] - b[u][w] * y[u][w];
+          ai[u] += g[u][w] * y[u][w] + b[u][w] * x[u][w];
+        }
+      q[u] += W;
+    }
+  }
+}
+
+// items per thread and row entries per round of the bus-indexed passes
+constexpr int kBusU = 1, kBusW = 4;
+
 // I = Y V, S = V conj(I), F1 = spec - calc on the block rows; ||F1||_inf per scenario.
 template <typename T, int S>
 __device__ __forceinline__ void phase_mismatch(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
                                unsigned char* scr) {
   double mx = 0.0;
   int bad = 0;
-  const int s = tid % S;
-  for (int idx = tid; idx < D.n_bus * S; idx += nt) {
-    const int i = idx / S;
-    double ir = 0.0, ii = 0.0;
-    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
-      const int j = m.y_ci[q];
-      const double g = m.y_g[q], b = m.y_b[q];
-      const double ej = c.e[sI<S>(j, s)], fj = c.f[sI<S>(j, s)];
-      ir += g * ej - b * fj;
-      ii += g * fj + b * ej;
+  const int s = tid % S, N = D.n_bus * S;
+  for (int base = tid; base < N; base += kBusU * nt) {
+    int i[kBusU], a[kBusU], bt[kBusU];
+    bool v[kBusU];
+    double ei[kBusU], fi[kBusU], ps[kBusU], qs[kBusU];
+#pragma unroll
+    for (int u = 0; u < kBusU; ++u) {
+      const int idx = base + u * nt;
+      v[u] = idx < N;
+      i[u] = v[u] ? idx / S : 0;
+      a[u] = m.bus_blk[i[u]];
+      bt[u] = m.bus_type[i[u]];
+      const int o = v[u] ? idx : base;
+      ei[u] = c.e[o];
+      fi[u] = c.f[o];
+      ps[u] = c.ps[o];
+      qs[u] = c.qs[o];
     }
-    c.ire[idx] = ir;
-    c.iim[idx] = ii;
-    const int a = m.bus_blk[i];
-    if (a >= 0) {
-      const double ei = c.e[idx], fi = c.f[idx];
-      const double P = ei * ir + fi * ii;
-      const double Q = fi * ir - ei * ii;
-      const double F0 = c.ps[idx] - P;
-      const double F1 = m.bus_type[i] == 0 ? c.qs[idx] - Q : 0.0;
-      c.F[sP<S>(a, s)] = F0;
-      c.F[sP<S>(a, s) + 1] = F1;
-      bad |= !(isfinite(F0) && isfinite(F1));
-      mx = fmax(mx, fmax(fabs(F0), fabs(F1)));
+    double ir[kBusU], ii[kBusU];
+    yrow_multi<S, kBusU, kBusW>(m, c.e, c.f, i, s, v, ir, ii);
+#pragma unroll
+    for (int u = 0; u < kBusU; ++u) {
+      if (!v[u]) continue;
+      const int idx = base + u * nt;
+      c.ire[idx] = ir[u];
+      c.iim[idx] = ii[u];
+      if (a[u] >= 0) {
+        const double P = ei[u] * ir[u] + fi[u] * ii[u];
+        const double Q = fi[u] * ir[u] - ei[u] * ii[u];
+        const double F0 = ps[u] - P;
+        const double F1 = bt[u] == 0 ? qs[u] - Q : 0.0;
+        c.F[sP<S>(a[u], s)] = F0;
+        c.F[sP<S>(a[u], s) + 1] = F1;
+        bad |= !(isfinite(F0) && isfinite(F1));
+        mx = fmax(mx, fmax(fabs(F0), fabs(F1)));
+      }
     }
   }
   __syncthreads();
@@ -381,20 +453,44 @@ __device__ __forceinline__ void phase_fill(const Sym& m, const Dims& D, St<T>& c
 // chunk of level metadata (tasks, steps, targets / rows, columns) into LDS
 // with the whole workgroup, so that only the value loads of a step reach HBM
 
-// metadata chunk c of a schedule: in place when the image is LDS-resident,
-// else copied into LDS by the whole workgroup; returns its base (int32)
+// The metadata chunks of a schedule, pass after pass: in place when the
+// image is LDS-resident, else copied into LDS by the whole workgroup.  The
+// copy of the next chunk is started before the current one is processed: its
+// first 16 bytes per lane are loaded into registers right after the chunk's
+// barrier, so their HBM/L2 latency overlaps the pass, and written to LDS at
+// the start of the next pass (the rest of a chunk larger than one int4 per
+// lane is copied there directly).
 template <bool STAGE>
-__device__ __forceinline__ const int* stage_chunk(const int* ptr, const int* blob, int c, unsigned char* lds,
-                                                  int tid, int nt) {
-  const int b0 = ptr[c];
-  if (!STAGE) return blob + b0;
-  const int b1 = ptr[c + 1];
-  int4* dst = reinterpret_cast<int4*>(lds);
-  const int4* src = reinterpret_cast<const int4*>(blob + b0);
-  for (int q = tid; q < ((b1 - b0) >> 2); q += nt) dst[q] = src[q];
-  __syncthreads();
-  return reinterpret_cast<const int*>(lds);
-}
+struct ChunkStager {
+  const int* ptr;
+  const int* blob;
+  int4* lds;
+  int tid, nt, nch;
+  int4 pre;     // this lane's first int4 of the next chunk
+  int b0, n4;   // the next chunk: start (int32 words) and length (int4)
+
+  __device__ __forceinline__ ChunkStager(const int* ptr_, const int* blob_, int nch_, unsigned char* lds_,
+                                         int tid_, int nt_)
+      : ptr(ptr_), blob(blob_), lds(reinterpret_cast<int4*>(lds_)), tid(tid_), nt(nt_), nch(nch_),
+        pre(make_int4(0, 0, 0, 0)), b0(0), n4(0) {
+    if (STAGE && nch > 0) fetch(0);
+  }
+  __device__ __forceinline__ void fetch(int c) {
+    b0 = ptr[c];
+    n4 = (ptr[c + 1] - b0) >> 2;
+    if (tid < n4) pre = reinterpret_cast<const int4*>(blob + b0)[tid];
+  }
+  // chunk c (in order c = 0, 1, ...): its base in LDS or in the image
+  __device__ __forceinline__ const int* get(int c) {
+    if (!STAGE) return blob + ptr[c];
+    const int4* src = reinterpret_cast<const int4*>(blob + b0);
+    if (tid < n4) lds[tid] = pre;
+    for (int q = tid + nt; q < n4; q += nt) lds[q] = src[q];
+    __syncthreads();
+    if (c + 1 < nch) fetch(c + 1);
+    return reinterpret_cast<const int*>(lds);
+  }
+};
 
 // Block LU (unit block-lower L, block-upper U with full 2x2 pivots) on the
 // fixed pattern, right-looking by levels with owner-computes rows: at level h
@@ -412,8 +508,9 @@ __device__ __forceinline__ const int* stage_chunk(const int* ptr, const int* blo
 template <typename T, int S, bool RES>
 __device__ __forceinline__ void phase_factor(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin,
                                              bool fwd, int* piv, unsigned char* lds) {
+  ChunkStager<!RES> stg(m.f_ptr, m.f_blob, D.nch_f, lds, tid, nt);
   for (int ch = 0; ch < D.nch_f; ++ch) {
-    const int* h = stage_chunk<!RES>(m.f_ptr, m.f_blob, ch, lds, tid, nt);
+    const int* h = stg.get(ch);
     const int ntask = h[0], nstep = h[1];
     const int4* tk4 = reinterpret_cast<const int4*>(h + 4);
     const int4* st4 = tk4 + ntask + 1;
@@ -500,8 +597,9 @@ __device__ __forceinline__ void phase_solve(const Sym& m, const Dims& D, St<T>& 
   const int nch = LOWER ? D.nch_fs : D.nch_bs;
   const int* ptr = LOWER ? m.fs_ptr : m.bs_ptr;
   const int* blob = LOWER ? m.fs_blob : m.bs_blob;
+  ChunkStager<!RES> stg(ptr, blob, nch, lds, tid, nt);
   for (int ch = 0; ch < nch; ++ch) {
-    const int* h = stage_chunk<!RES>(ptr, blob, ch, lds, tid, nt);
+    const int* h = stg.get(ch);
     const int nrow = h[0];
     const int4* rw = reinterpret_cast<const int4*>(h + 4);
     const int* cols = reinterpret_cast<const int*>(rw + nrow + 1);
@@ -952,21 +1050,41 @@ __device__ __forceinline__ void rt_bsolve(const Sym& m, const Dims& D, St<T>& c,
   if (l < t) c.y[sP<S>(tb + l, s) + h] = y;
 }
 
-// dV = V (d|V|/|V| + j dtheta) for the correction dx (slack: 0)
+// dV = V (d|V|/|V| + j dtheta) for the correction dx (slack: 0); four items
+// per thread, loads first
 template <typename T, int S>
 __device__ __forceinline__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
-  for (int idx = tid; idx < D.n_bus * S; idx += nt) {
-    const int i = idx / S, s = idx % S;
-    const int a = m.bus_blk[i];
-    double dvr = 0.0, dvi = 0.0;
-    if (a >= 0) {
-      const double dth = c.dx[sP<S>(a, s)];
-      const double rho = m.bus_type[i] == 0 ? c.dx[sP<S>(a, s) + 1] * c.rvm[idx] : 0.0;
-      dvr = c.e[idx] * rho - c.f[idx] * dth;
-      dvi = c.f[idx] * rho + c.e[idx] * dth;
+  constexpr int U = 4;
+  const int s = tid % S, N = D.n_bus * S;
+  for (int base = tid; base < N; base += U * nt) {
+    double dth[U], dvm[U], rv[U], e[U], f[U];
+    int a[U], bt[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * nt;
+      const int o = idx < N ? idx : base;
+      a[u] = m.bus_blk[o / S];
+      bt[u] = m.bus_type[o / S];
+      const int pa = a[u] >= 0 ? a[u] : 0;
+      dth[u] = c.dx[sP<S>(pa, s)];
+      dvm[u] = c.dx[sP<S>(pa, s) + 1];
+      rv[u] = c.rvm[o];
+      e[u] = c.e[o];
+      f[u] = c.f[o];
     }
-    c.dvr[idx] = dvr;
-    c.dvi[idx] = dvi;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * nt;
+      if (idx >= N) continue;
+      double dvr = 0.0, dvi = 0.0;
+      if (a[u] >= 0) {
+        const double rho = bt[u] == 0 ? dvm[u] * rv[u] : 0.0;
+        dvr = e[u] * rho - f[u] * dth[u];
+        dvi = f[u] * rho + e[u] * dth[u];
+      }
+      c.dvr[idx] = dvr;
+      c.dvi[idx] = dvi;
+    }
   }
   __syncthreads();
 }
@@ -978,27 +1096,43 @@ template <typename T, int S>
 __device__ __forceinline__ void phase_residual(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
                                                bool norm, unsigned char* scr) {
   double mx = 0.0;
-  for (int idx = tid; idx < D.n_bus * S; idx += nt) {
-    const int i = idx / S, s = idx % S;
-    const int a = m.bus_blk[i];
-    if (a < 0) continue;
-    double dir = 0.0, dii = 0.0;
-    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
-      const int j = sI<S>(m.y_ci[q], s);
-      const double g = m.y_g[q], b = m.y_b[q];
-      dir += g * c.dvr[j] - b * c.dvi[j];
-      dii += g * c.dvi[j] + b * c.dvr[j];
+  const int s = tid % S, N = D.n_bus * S;
+  for (int base = tid; base < N; base += kBusU * nt) {
+    int i[kBusU], a[kBusU], bt[kBusU];
+    bool v[kBusU];
+    double e[kBusU], f[kBusU], ir[kBusU], ii[kBusU], dvr[kBusU], dvi[kBusU], F0[kBusU], F1[kBusU];
+#pragma unroll
+    for (int u = 0; u < kBusU; ++u) {
+      const int idx = base + u * nt;
+      const int o = idx < N ? idx : base;
+      i[u] = o / S;
+      a[u] = m.bus_blk[i[u]];
+      bt[u] = m.bus_type[i[u]];
+      v[u] = idx < N && a[u] >= 0;
+      e[u] = c.e[o];
+      f[u] = c.f[o];
+      ir[u] = c.ire[o];
+      ii[u] = c.iim[o];
+      dvr[u] = c.dvr[o];
+      dvi[u] = c.dvi[o];
+      const int pa = a[u] >= 0 ? a[u] : 0;
+      F0[u] = c.F[sP<S>(pa, s)];
+      F1[u] = c.F[sP<S>(pa, s) + 1];
     }
-    const double e = c.e[idx], f = c.f[idx], ir = c.ire[idx], ii = c.iim[idx];
-    const double dvr = c.dvr[idx], dvi = c.dvi[idx];
-    const double dSr = dvr * ir + dvi * ii + e * dir + f * dii;
-    const double dSi = dvi * ir - dvr * ii + f * dir - e * dii;
-    const int o = sP<S>(a, s);
-    const double r0 = -c.F[o] + dSr;
-    const double r1 = m.bus_type[i] == 0 ? -c.F[o + 1] + dSi : 0.0;
-    c.y[o] = T(r0);
-    c.y[o + 1] = T(r1);
-    mx = fmax(mx, fmax(fabs(r0), fabs(r1)));
+    double dir[kBusU], dii[kBusU];
+    yrow_multi<S, kBusU, kBusW>(m, c.dvr, c.dvi, i, s, v, dir, dii);
+#pragma unroll
+    for (int u = 0; u < kBusU; ++u) {
+      if (!v[u]) continue;
+      const double dSr = dvr[u] * ir[u] + dvi[u] * ii[u] + e[u] * dir[u] + f[u] * dii[u];
+      const double dSi = dvi[u] * ir[u] - dvr[u] * ii[u] + f[u] * dir[u] - e[u] * dii[u];
+      const int o = sP<S>(a[u], s);
+      const double r0 = -F0[u] + dSr;
+      const double r1 = bt[u] == 0 ? -F1[u] + dSi : 0.0;
+      c.y[o] = T(r0);
+      c.y[o + 1] = T(r1);
+      mx = fmax(mx, fmax(fabs(r0), fabs(r1)));
+    }
   }
   __syncthreads();
   if (norm) block_max<S>(mx, 0, scr, tid, nt);
@@ -1362,8 +1496,9 @@ __device__ __forceinline__ void phase_tsolve(const AdjSym& a, const Dims& D, St<
   const int nch = UT ? D.nch_ut : D.nch_lt;
   const int* ptr = UT ? a.ut_ptr : a.lt_ptr;
   const int* blob = UT ? a.ut_blob : a.lt_blob;
+  ChunkStager<!RES> stg(ptr, blob, nch, lds, tid, nt);
   for (int ch = 0; ch < nch; ++ch) {
-    const int* h = stage_chunk<!RES>(ptr, blob, ch, lds, tid, nt);
+    const int* h = stg.get(ch);
     const int nrow = h[0];
     const int4* rw = reinterpret_cast<const int4*>(h + 4);
     const int* cols = reinterpret_cast<const int*>(rw + nrow + 1);
