@@ -91,13 +91,23 @@ constexpr int32_t kChunkInts = 12288;
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-sable::StateLayout make_layout(int n_bus, int nb, int nnzb) {
+// HBM workspace of a scenario (also the layout of the interleaved slice
+// workspace).  grouped: the eight per-bus values that the gathers read (e f
+// |V| 1/|V| I_re I_im dV_re dV_im) sit together by bus, so that a gather of a
+// bus reads one run per scenario instead of one per value.  That pays off for
+// slices of several scenarios, whose bus-order passes still read whole runs;
+// a slice of one scenario keeps one array per value, so that its bus-order
+// passes read consecutive buses of one array.
+sable::StateLayout make_layout(int n_bus, int nb, int nnzb, bool grouped) {
   sable::StateLayout L{};
   const int nbr = round_up(n_bus, 4), v2 = round_up(2 * nb, 4);
   int o = 0;
-  L.o_e = o; o += nbr; L.o_f = o; o += nbr; L.o_vm = o; o += nbr; L.o_va = o; o += nbr;
-  L.o_ire = o; o += nbr; L.o_iim = o; o += nbr; L.o_ps = o; o += nbr; L.o_qs = o; o += nbr;
-  L.o_dvr = o; o += nbr; L.o_dvi = o; o += nbr; L.o_aux = o; o += nbr; L.o_rvm = o; o += nbr;
+  L.gk = grouped ? 8 : 1;
+  const int fs = grouped ? 1 : nbr;   // offset between consecutive values of a bus
+  L.o_e = o; L.o_f = o + fs; L.o_vm = o + 2 * fs; L.o_rvm = o + 3 * fs;
+  L.o_ire = o + 4 * fs; L.o_iim = o + 5 * fs; L.o_dvr = o + 6 * fs; L.o_dvi = o + 7 * fs;
+  o += 8 * nbr;
+  L.o_va = o; o += nbr; L.o_ps = o; o += nbr; L.o_qs = o; o += nbr; L.o_aux = o; o += nbr;
   L.o_F = o; o += v2; L.o_dx = o; o += v2;
   L.sd = o;
   int t = 0;
@@ -112,6 +122,7 @@ sable::StateLayout make_layout(int n_bus, int nb, int nnzb) {
 // vectors only exist in the mixed-precision mode, the adjoint scratch never
 sable::StateLayout make_lds_layout(int n_bus, int nb, int nnzb, bool mixed) {
   sable::StateLayout L{};
+  L.gk = 1;
   int o = 0;
   L.o_e = o; o += n_bus; L.o_f = o; o += n_bus; L.o_vm = o; o += n_bus; L.o_va = o; o += n_bus;
   L.o_ire = o; o += n_bus; L.o_iim = o; o += n_bus; L.o_ps = o; o += n_bus; L.o_qs = o; o += n_bus;
@@ -136,6 +147,7 @@ sable::StateLayout make_lds_layout(int n_bus, int nb, int nnzb, bool mixed) {
 // (e f |V|), the currents, the adjoint scratch and the factors
 sable::StateLayout make_adj_layout(int n_bus, int nb, int nnzb) {
   sable::StateLayout L{};
+  L.gk = 1;
   int o = 0;
   L.o_e = o; o += n_bus; L.o_f = o; o += n_bus; L.o_vm = o; o += n_bus;
   L.o_ire = o; o += n_bus; L.o_iim = o; o += n_bus;
@@ -474,7 +486,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   // one wavefront per scenario's register-resident tail) when they fit,
   // choosing S to maximise the scenarios resident per CU; HBM-resident
   // slices of up to 16 scenarios otherwise
-  t->lay = make_layout(S.n_bus, S.nb, S.nnzb());
+  t->lay = make_layout(S.n_bus, S.nb, S.nnzb(), false);
   t->llay = make_lds_layout(S.n_bus, S.nb, S.nnzb(), t->fp32);
   const size_t lds_cu = std::max<size_t>(max_lds, (size_t)prop.maxSharedMemoryPerMultiProcessor);
   const size_t per_scen = 8 * (size_t)t->llay.sd + tsz * (size_t)t->llay.st;
@@ -517,6 +529,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     t->lds_res = false;
     const int sl = hbm_slice;
     t->slice = sl;
+    t->lay = make_layout(S.n_bus, S.nb, S.nnzb(), sl > 1);
     t->lds_bytes = sable::kScratchBytes + 4 * (size_t)chunks.max_ints + tail_bytes(sl);
     // the adjoint reads this slice workspace in place
     t->adj_slice = -sl;

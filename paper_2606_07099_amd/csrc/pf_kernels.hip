@@ -142,10 +142,18 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
 }
 
 // per-slice state; element k of scenario s sits at k*S + s
+// per-slice state.  e f |V| 1/|V| I_re I_im dV_re dV_im of bus i, scenario s
+// sit at index i * gs + s of their arrays (g(i, s) below): gs = S when every
+// array is interleaved on its own (LDS-resident slices), 8 S when a bus's eight
+// values are grouped (HBM-resident slices: a gather of one bus then touches
+// one 64-byte run per scenario instead of one per value).  The other arrays
+// are interleaved by scenario: element k of scenario s at k * S + s.
 template <typename T>
 struct St {
   double *e, *f, *vm, *va, *ire, *iim, *ps, *qs, *dvr, *dvi, *aux, *rvm, *F, *dx;
   T *y, *lu, *dinv;
+  int gs;
+  __device__ __forceinline__ int g(int i, int s) const { return i * gs + s; }
 };
 
 template <typename T, int S>
@@ -156,6 +164,7 @@ __device__ __forceinline__ St<T> bind_state(double* d, T* t, const StateLayout& 
   c.dvr = d + L.o_dvr * S; c.dvi = d + L.o_dvi * S; c.aux = d + L.o_aux * S; c.rvm = d + L.o_rvm * S;
   c.F = d + L.o_F * S; c.dx = d + L.o_dx * S;
   c.y = t + L.o_y * S; c.lu = t + L.o_lu * S; c.dinv = t + L.o_dinv * S;
+  c.gs = L.gk * S;
   return c;
 }
 
@@ -201,7 +210,7 @@ __device__ __forceinline__ void fill_gather(const Sym& m, const St<T>& c, int s,
   const bool dg = r.w & 1;
   q.g = r.x < 0 ? 0.0 : m.y_g[r.x];
   q.b = r.x < 0 ? 0.0 : m.y_b[r.x];
-  const int is = sI<S>(r.y, s), ms = sI<S>(r.z, s);
+  const int is = c.g(r.y, s), ms = c.g(r.z, s);
   q.x[0] = c.e[is];
   q.x[1] = c.f[is];
   if (dg) {
@@ -320,8 +329,9 @@ __device__ __forceinline__ void block_max(double v, int bad, unsigned char* scr,
 // of the round loaded before the arithmetic.  Entries past a row's end load
 // bus 0 (in bounds) and are not added; each row is summed in column order.
 template <int S, int U, int W>
-__device__ __forceinline__ void yrow_multi(const Sym& m, const double* xr, const double* xi, const int (&i)[U],
-                                           int s, const bool (&v)[U], double (&ar)[U], double (&ai)[U]) {
+__device__ __forceinline__ void yrow_multi(const Sym& m, const double* xr, const double* xi, int gs,
+                                           const int (&i)[U], int s, const bool (&v)[U], double (&ar)[U],
+                                           double (&ai)[U]) {
   int q[U], q1[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -350,8 +360,8 @@ __device__ __forceinline__ void yrow_multi(const Sym& m, const double* xr, const
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        x[u][w] = xr[sI<S>(j[u][w], s)];
-        y[u][w] = xi[sI<S>(j[u][w], s)];
+        x[u][w] = xr[j[u][w] * gs + s];
+        y[u][w] = xi[j[u][w] * gs + s];
       }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -369,8 +379,9 @@ __device__ __forceinline__ void yrow_multi(const Sym& m, const double* xr, const
 // items per thread and row entries per round of the bus-indexed passes
 constexpr int kBusU = 1, kBusW = 4;
 
-// I = Y V, S = V conj(I), F1 = spec - calc on the block rows; ||F1||_inf per scenario.
-template <typename T, int S>
+// I = Y V, S = V conj(I), F1 = spec - calc on the block rows; ||F1||_inf per
+// scenario.  With RHS the Newton step's right-hand side y = -F1 is written too.
+template <typename T, int S, bool RHS>
 __device__ __forceinline__ void phase_mismatch(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
                                unsigned char* scr) {
   double mx = 0.0;
@@ -388,19 +399,20 @@ __device__ __forceinline__ void phase_mismatch(const Sym& m, const Dims& D, St<T
       a[u] = m.bus_blk[i[u]];
       bt[u] = m.bus_type[i[u]];
       const int o = v[u] ? idx : base;
-      ei[u] = c.e[o];
-      fi[u] = c.f[o];
+      const int go = c.g(i[u], s);
+      ei[u] = c.e[go];
+      fi[u] = c.f[go];
       ps[u] = c.ps[o];
       qs[u] = c.qs[o];
     }
     double ir[kBusU], ii[kBusU];
-    yrow_multi<S, kBusU, kBusW>(m, c.e, c.f, i, s, v, ir, ii);
+    yrow_multi<S, kBusU, kBusW>(m, c.e, c.f, c.gs, i, s, v, ir, ii);
 #pragma unroll
     for (int u = 0; u < kBusU; ++u) {
       if (!v[u]) continue;
-      const int idx = base + u * nt;
-      c.ire[idx] = ir[u];
-      c.iim[idx] = ii[u];
+      const int go = c.g(i[u], s);
+      c.ire[go] = ir[u];
+      c.iim[go] = ii[u];
       if (a[u] >= 0) {
         const double P = ei[u] * ir[u] + fi[u] * ii[u];
         const double Q = fi[u] * ir[u] - ei[u] * ii[u];
@@ -408,6 +420,10 @@ __device__ __forceinline__ void phase_mismatch(const Sym& m, const Dims& D, St<T
         const double F1 = bt[u] == 0 ? qs[u] - Q : 0.0;
         c.F[sP<S>(a[u], s)] = F0;
         c.F[sP<S>(a[u], s) + 1] = F1;
+        if (RHS) {
+          c.y[sP<S>(a[u], s)] = T(-F0);
+          c.y[sP<S>(a[u], s) + 1] = T(-F1);
+        }
         bad |= !(isfinite(F0) && isfinite(F1));
         mx = fmax(mx, fmax(fabs(F0), fabs(F1)));
       }
@@ -591,9 +607,12 @@ __device__ __forceinline__ void phase_factor(const Sym& m, const Dims& D, St<T>&
 // level-scheduled row solves of the rows outside the dense tail, rows and
 // their columns from the metadata chunks: forward (unit block-lower L, in
 // place in y) or backward (U with the inverted pivot blocks)
+// The backward pass can also hand its result to the FP64 correction of the
+// scenarios in `mask`: dxmode 1 sets dx = y, dxmode 2 adds y to dx (each row
+// is written once, by its lane of entry 0, so no separate copy pass is needed).
 template <typename T, int S, bool RES, bool LOWER>
 __device__ __forceinline__ void phase_solve(const Sym& m, const Dims& D, St<T>& c, int tid, int nt, int gmin,
-                                            unsigned char* lds) {
+                                            unsigned char* lds, int dxmode = 0, int mask = 0) {
   const int nch = LOWER ? D.nch_fs : D.nch_bs;
   const int* ptr = LOWER ? m.fs_ptr : m.bs_ptr;
   const int* blob = LOWER ? m.fs_blob : m.bs_blob;
@@ -609,8 +628,43 @@ __device__ __forceinline__ void phase_solve(const Sym& m, const Dims& D, St<T>& 
     for (int ri = g.gid; ri < nrow; ri += g.ng) {
       const int4 r = rw[ri];   // row, first position, -, first column
       const int a = r.x, n = rw[ri + 1].w - r.w;
+      // the row's own right-hand side (and, backward, its pivot inverse and
+      // the correction it adds to) are loaded before the dot product, so
+      // that their latency overlaps it
+      T ya0 = T(0), ya1 = T(0);
+      Blk<T> Di = {T(0), T(0), T(0), T(0)};
+      double dx0 = 0.0, dx1 = 0.0;
+      if (e == 0) {
+        ya0 = c.y[sP<S>(a, s)];
+        ya1 = c.y[sP<S>(a, s) + 1];
+        if (!LOWER) Di = ld_blk(c.dinv + sB<S>(a, s));
+        if (!LOWER && dxmode == 2) {
+          dx0 = c.dx[sP<S>(a, s)];
+          dx1 = c.dx[sP<S>(a, s) + 1];
+        }
+      }
       T s0 = T(0), s1 = T(0);
-      for (int j = e; j < n; j += E) {
+      int j = e;
+      // HBM-resident slices: two entries per round, loads first, summed in
+      // order (in LDS the loads return quickly and the plain loop is shorter)
+      for (; !RES && j + E < n; j += 2 * E) {
+        Blk<T> M[2];
+        T z[2][2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int p = r.y + j + u * E;
+          M[u] = ld_blk_nt(c.lu + sB<S>(p, s));
+          const int k = cols[r.w + j + u * E];
+          z[u][0] = c.y[sP<S>(k, s)];
+          z[u][1] = c.y[sP<S>(k, s) + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          s0 += M[u].a * z[u][0] + M[u].b * z[u][1];
+          s1 += M[u].c * z[u][0] + M[u].d * z[u][1];
+        }
+      }
+      for (; j < n; j += E) {
         const Blk<T> M = RES ? ld_blk(c.lu + sB<S>(r.y + j, s)) : ld_blk_nt(c.lu + sB<S>(r.y + j, s));
         const int k = cols[r.w + j];
         const T z0 = c.y[sP<S>(k, s)], z1 = c.y[sP<S>(k, s) + 1];
@@ -621,13 +675,20 @@ __device__ __forceinline__ void phase_solve(const Sym& m, const Dims& D, St<T>& 
       s1 = group_sum<T, S>(s1, G);
       if (e == 0) {
         if (LOWER) {
-          c.y[sP<S>(a, s)] -= s0;
-          c.y[sP<S>(a, s) + 1] -= s1;
+          c.y[sP<S>(a, s)] = ya0 - s0;
+          c.y[sP<S>(a, s) + 1] = ya1 - s1;
         } else {
-          const Blk<T> Di = ld_blk(c.dinv + sB<S>(a, s));
-          const T t0 = c.y[sP<S>(a, s)] - s0, t1 = c.y[sP<S>(a, s) + 1] - s1;
-          c.y[sP<S>(a, s)] = Di.a * t0 + Di.b * t1;
-          c.y[sP<S>(a, s) + 1] = Di.c * t0 + Di.d * t1;
+          const T t0 = ya0 - s0, t1 = ya1 - s1;
+          const T x0 = Di.a * t0 + Di.b * t1, x1 = Di.c * t0 + Di.d * t1;
+          c.y[sP<S>(a, s)] = x0;
+          c.y[sP<S>(a, s) + 1] = x1;
+          if (dxmode == 1) {
+            c.dx[sP<S>(a, s)] = double(x0);
+            c.dx[sP<S>(a, s) + 1] = double(x1);
+          } else if (dxmode == 2 && ((mask >> s) & 1)) {
+            c.dx[sP<S>(a, s)] = dx0 + double(x0);
+            c.dx[sP<S>(a, s) + 1] = dx1 + double(x1);
+          }
         }
       }
     }
@@ -781,12 +842,17 @@ __device__ __forceinline__ void ltail_fsolve(const Sym& m, const Dims& D, St<T>&
 
 template <typename T, int S>
 __device__ __forceinline__ void ltail_bsolve(const Sym& m, const Dims& D, St<T>& c, const T* tl, const T* td,
-                                             int tid, int nt) {
+                                             int tid, int nt, int dxmode = 0, int mask = 0) {
   const int t = D.tail_t, tb = D.tail_base;
   const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
   for (int s = w; s < S; s += nw) {
     T y0 = T(0), y1 = T(0);
-    if (l < t) { y0 = c.y[sP<S>(tb + l, s)]; y1 = c.y[sP<S>(tb + l, s) + 1]; }
+    double dx0 = 0.0, dx1 = 0.0;
+    if (l < t) {
+      y0 = c.y[sP<S>(tb + l, s)];
+      y1 = c.y[sP<S>(tb + l, s) + 1];
+      if (dxmode == 2) { dx0 = c.dx[sP<S>(tb + l, s)]; dx1 = c.dx[sP<S>(tb + l, s) + 1]; }
+    }
     for (int j = t - 1; j >= 0; --j) {
       if (l == j) {
         const Blk<T> Di = ld_blk(td + sB<S>(j, s));
@@ -804,7 +870,17 @@ __device__ __forceinline__ void ltail_bsolve(const Sym& m, const Dims& D, St<T>&
         }
       }
     }
-    if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+    if (l < t) {
+      c.y[sP<S>(tb + l, s)] = y0;
+      c.y[sP<S>(tb + l, s) + 1] = y1;
+      if (dxmode == 1) {
+        c.dx[sP<S>(tb + l, s)] = double(y0);
+        c.dx[sP<S>(tb + l, s) + 1] = double(y1);
+      } else if (dxmode == 2 && ((mask >> s) & 1)) {
+        c.dx[sP<S>(tb + l, s)] = dx0 + double(y0);
+        c.dx[sP<S>(tb + l, s) + 1] = dx1 + double(y1);
+      }
+    }
   }
 }
 
@@ -1026,12 +1102,16 @@ __device__ __forceinline__ void rt_fsolve(const Sym& m, const Dims& D, St<T>& c,
 // backward solve of the tail block, the last unknown first
 template <typename T, int S>
 __device__ __forceinline__ void rt_bsolve(const Sym& m, const Dims& D, St<T>& c, int s, int ln,
-                                          const TailRow<T>& R) {
+                                          const TailRow<T>& R, int dxmode = 0, int mask = 0) {
   const int t = __builtin_amdgcn_readfirstlane(D.tail_t), tb = D.tail_base;
   if (t == 0) return;
   const int l = lane_row(ln), h = ln & 1;
   T y = T(0);
-  if (l < t) y = c.y[sP<S>(tb + l, s) + h];
+  double dxo = 0.0;
+  if (l < t) {
+    y = c.y[sP<S>(tb + l, s) + h];
+    if (dxmode == 2) dxo = c.dx[sP<S>(tb + l, s) + h];
+  }
   const unsigned cm = __builtin_amdgcn_readfirstlane(m.tail_mask[t + 1]);   // columns with U blocks
 #pragma unroll
   for (int j = tail_cap<T>() - 1; j >= 0; --j) {
@@ -1047,7 +1127,11 @@ __device__ __forceinline__ void rt_bsolve(const Sym& m, const Dims& D, St<T>& c,
       }
     }
   }
-  if (l < t) c.y[sP<S>(tb + l, s) + h] = y;
+  if (l < t) {
+    c.y[sP<S>(tb + l, s) + h] = y;
+    if (dxmode == 1) c.dx[sP<S>(tb + l, s) + h] = double(y);
+    else if (dxmode == 2 && ((mask >> s) & 1)) c.dx[sP<S>(tb + l, s) + h] = dxo + double(y);
+  }
 }
 
 // dV = V (d|V|/|V| + j dtheta) for the correction dx (slack: 0); four items
@@ -1066,11 +1150,12 @@ __device__ __forceinline__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, 
       a[u] = m.bus_blk[o / S];
       bt[u] = m.bus_type[o / S];
       const int pa = a[u] >= 0 ? a[u] : 0;
+      const int go = c.g(o / S, s);
       dth[u] = c.dx[sP<S>(pa, s)];
       dvm[u] = c.dx[sP<S>(pa, s) + 1];
-      rv[u] = c.rvm[o];
-      e[u] = c.e[o];
-      f[u] = c.f[o];
+      rv[u] = c.rvm[go];
+      e[u] = c.e[go];
+      f[u] = c.f[go];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1082,8 +1167,9 @@ __device__ __forceinline__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, 
         dvr = e[u] * rho - f[u] * dth[u];
         dvi = f[u] * rho + e[u] * dth[u];
       }
-      c.dvr[idx] = dvr;
-      c.dvi[idx] = dvi;
+      const int go = c.g(idx / S, s);
+      c.dvr[go] = dvr;
+      c.dvi[go] = dvi;
     }
   }
   __syncthreads();
@@ -1109,18 +1195,19 @@ __device__ __forceinline__ void phase_residual(const Sym& m, const Dims& D, St<T
       a[u] = m.bus_blk[i[u]];
       bt[u] = m.bus_type[i[u]];
       v[u] = idx < N && a[u] >= 0;
-      e[u] = c.e[o];
-      f[u] = c.f[o];
-      ir[u] = c.ire[o];
-      ii[u] = c.iim[o];
-      dvr[u] = c.dvr[o];
-      dvi[u] = c.dvi[o];
+      const int go = c.g(i[u], s);
+      e[u] = c.e[go];
+      f[u] = c.f[go];
+      ir[u] = c.ire[go];
+      ii[u] = c.iim[go];
+      dvr[u] = c.dvr[go];
+      dvi[u] = c.dvi[go];
       const int pa = a[u] >= 0 ? a[u] : 0;
       F0[u] = c.F[sP<S>(pa, s)];
       F1[u] = c.F[sP<S>(pa, s) + 1];
     }
     double dir[kBusU], dii[kBusU];
-    yrow_multi<S, kBusU, kBusW>(m, c.dvr, c.dvi, i, s, v, dir, dii);
+    yrow_multi<S, kBusU, kBusW>(m, c.dvr, c.dvi, c.gs, i, s, v, dir, dii);
 #pragma unroll
     for (int u = 0; u < kBusU; ++u) {
       if (!v[u]) continue;
@@ -1160,12 +1247,13 @@ template <typename T, int S>
 __device__ __forceinline__ void phase_set_state(const Dims& D, St<T>& c, int tid, int nt, int mask) {
   for (int idx = tid; idx < D.n_bus * S; idx += nt) {
     if (!((mask >> (idx % S)) & 1)) continue;
+    const int o = c.g(idx / S, idx % S);
     double sn, cs;
     sincos(c.va[idx], &sn, &cs);
-    const double v = c.vm[idx];
-    c.e[idx] = v * cs;
-    c.f[idx] = v * sn;
-    c.rvm[idx] = 1.0 / v;
+    const double v = c.vm[o];
+    c.e[o] = v * cs;
+    c.f[o] = v * sn;
+    c.rvm[o] = 1.0 / v;
   }
   __syncthreads();
 }
@@ -1224,16 +1312,16 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       c.ps[idx] = pg - kp.pd[o];
       c.qs[idx] = -kp.qd[o];
       if (kp.mode == MODE_SOLVE) {
-        c.vm[idx] = bt == 0 ? 1.0 : kp.vset[o];
+        c.vm[c.g(i, s)] = bt == 0 ? 1.0 : kp.vset[o];
         c.va[idx] = 0.0;
       } else {
-        c.vm[idx] = kp.vm_in[o];
+        c.vm[c.g(i, s)] = kp.vm_in[o];
         c.va[idx] = bt == 2 ? 0.0 : kp.va_in[o];
       }
     } else {
       c.ps[idx] = 0.0;
       c.qs[idx] = 0.0;
-      c.vm[idx] = 1.0;
+      c.vm[c.g(i, s)] = 1.0;
       c.va[idx] = 0.0;
     }
   }
@@ -1250,7 +1338,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
   TailRow<T> R;                             // this wavefront's factored tail rows
   pc.mark(PH_SETUP);
   while (true) {
-    phase_mismatch<T, S>(m, D, c, tid, nt, scr);
+    phase_mismatch<T, S, (S > 1 && !RES)>(m, D, c, tid, nt, scr);
     pc.mark(PH_MISMATCH);
     for (int s = 0; s < S; ++s) {
       if (!((act >> s) & 1)) continue;
@@ -1271,7 +1359,16 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       break;
     }
     if (!act) break;
-    for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
+    // slices of several scenarios form y = -F1 in the mismatch pass and hand
+    // the backward solves' results to dx as they write them; a slice of one
+    // scenario scatters each of those stores to its own line, on the critical
+    // path of a level, so it runs them as separate streaming passes instead
+    constexpr bool fuse = S > 1 && !RES;
+    constexpr int dx_set = fuse ? 1 : 0, dx_add = fuse ? 2 : 0;
+    if (!fuse) {
+      for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
+      __syncthreads();
+    }
     phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
     pc.mark(PH_FILL);
     pc.count(PH_NEWTON_STEPS);
@@ -1293,16 +1390,18 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       }
     if (!act) break;
     if constexpr (RES) {
-      if (wv < S) rt_bsolve<T, S>(m, D, c, wv, ln, R);
+      if (wv < S) rt_bsolve<T, S>(m, D, c, wv, ln, R, dx_set);
     } else {
-      ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt);
+      ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt, dx_set);
     }
     __syncthreads();
     pc.mark(PH_BSOLVE_TAIL);
-    phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg);
+    phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg, dx_set);   // dx = y as well
     pc.mark(PH_BSOLVE_LEVELS);
-    for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
-    __syncthreads();
+    if (!fuse) {
+      for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
+      __syncthreads();
+    }
     if (mixed) {
       int ref = act;   // scenarios still refining their correction
       for (int r = 0; r < kp.refine; ++r) {
@@ -1327,34 +1426,45 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
         if constexpr (RES) {
           if (wv < S) {
             rt_fsolve<T, S>(m, D, c, wv, ln, R);
-            rt_bsolve<T, S>(m, D, c, wv, ln, R);
+            rt_bsolve<T, S>(m, D, c, wv, ln, R, dx_add, ref);
           }
         } else {
           ltail_fsolve<T, S>(m, D, c, tl, tid, nt);
           __syncthreads();
-          ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt);
+          ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt, dx_add, ref);
         }
         __syncthreads();
         pc.mark(PH_REFINE_TAIL);
-        phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg);
+        phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg, dx_add, ref);   // dx += y as well
         pc.mark(PH_REFINE_BSOLVE_LEVELS);
-        for (int q = tid; q < 2 * nb * S; q += nt)
-          if ((ref >> ((q >> 1) % S)) & 1) c.dx[q] += double(c.y[q]);
-        __syncthreads();
+        if (!fuse) {
+          for (int q = tid; q < 2 * nb * S; q += nt)
+            if ((ref >> ((q >> 1) % S)) & 1) c.dx[q] += double(c.y[q]);
+          __syncthreads();
+        }
       }
     }
     if (kp.mode == MODE_EVAL_STEP) break;
-    // state update of the active scenarios: theta on non-slack buses, |V| on PQ buses
+    // state update of the active scenarios (theta on non-slack buses, |V| on
+    // PQ buses) and their e + jf, by the thread that owns the item in both
     for (int idx = tid; idx < n * S; idx += nt) {
       const int i = idx / S, s = idx % S;
-      const int a = m.bus_blk[i];
-      if (a >= 0 && ((act >> s) & 1)) {
-        c.va[idx] += c.dx[sP<S>(a, s)];
-        if (m.bus_type[i] == 0) c.vm[idx] += c.dx[sP<S>(a, s) + 1];
+      if (!((act >> s) & 1)) continue;
+      const int a = m.bus_blk[i], o = c.g(i, s);
+      double va = c.va[idx], vm = c.vm[o];
+      if (a >= 0) {
+        va += c.dx[sP<S>(a, s)];
+        if (m.bus_type[i] == 0) vm += c.dx[sP<S>(a, s) + 1];
+        c.va[idx] = va;
+        c.vm[o] = vm;
       }
+      double sn, cs;
+      sincos(va, &sn, &cs);
+      c.e[o] = vm * cs;
+      c.f[o] = vm * sn;
+      c.rvm[o] = 1.0 / vm;
     }
     __syncthreads();
-    phase_set_state<T, S>(D, c, tid, nt, act);
     if (tid < S && ((act >> tid) & 1)) s_it[tid]++;
     pc.mark(PH_OTHER);
   }
@@ -1367,7 +1477,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       const int i = idx / S, s = idx % S;
       const int b = slice * S + s;
       if (b < kp.count) {
-        kp.vm_out[(size_t)b * n + i] = c.vm[idx];
+        kp.vm_out[(size_t)b * n + i] = c.vm[c.g(i, s)];
         kp.va_out[(size_t)b * n + i] = c.va[idx];
       }
     }
@@ -1435,9 +1545,10 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
         for (int q = tid; q < 4 * D.nnzb; q += nt) gt[kp.lay.o_lu + q] = c.lu[sB<S>(q >> 2, s) + (q & 3)];
         for (int q = tid; q < 4 * nb; q += nt) gt[kp.lay.o_dinv + q] = c.dinv[sB<S>(q >> 2, s) + (q & 3)];
         for (int i = tid; i < n; i += nt) {
-          gd[kp.lay.o_e + i] = c.e[sI<S>(i, s)];
-          gd[kp.lay.o_f + i] = c.f[sI<S>(i, s)];
-          gd[kp.lay.o_vm + i] = c.vm[sI<S>(i, s)];
+          const int gi = i * kp.lay.gk;   // the per-scenario workspace groups them
+          gd[kp.lay.o_e + gi] = c.e[c.g(i, s)];
+          gd[kp.lay.o_f + gi] = c.f[c.g(i, s)];
+          gd[kp.lay.o_vm + gi] = c.vm[c.g(i, s)];
           gd[kp.lay.o_va + i] = c.va[sI<S>(i, s)];
         }
       }
@@ -1508,8 +1619,34 @@ __device__ __forceinline__ void phase_tsolve(const AdjSym& a, const Dims& D, St<
     for (int ri = g.gid; ri < nrow; ri += g.ng) {
       const int4 r = rw[ri];   // row, -, -, first pair
       const int row = r.x, n = rw[ri + 1].w - r.w;
+      // the row's own right-hand side (and, for U^T, its pivot inverse)
+      // loaded before the dot product, whose latency they then overlap
+      T ya0 = T(0), ya1 = T(0);
+      Blk<T> Di = {T(0), T(0), T(0), T(0)};
+      if (e == 0) {
+        ya0 = c.y[sP<S>(row, s)];
+        ya1 = c.y[sP<S>(row, s) + 1];
+        if (UT) Di = ld_blk(c.dinv + sB<S>(row, s));
+      }
       T s0 = T(0), s1 = T(0);
-      for (int j = e; j < n; j += E) {
+      int j = e;
+      for (; !RES && j + E < n; j += 2 * E) {   // HBM: two entries per round, loads first, in order
+        Blk<T> B[2];
+        T z[2][2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int k = cols[2 * (r.w + j + u * E)], mp = cols[2 * (r.w + j + u * E) + 1];
+          B[u] = ld_blk(c.lu + sB<S>(mp, s));
+          z[u][0] = c.y[sP<S>(k, s)];
+          z[u][1] = c.y[sP<S>(k, s) + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          s0 += B[u].a * z[u][0] + B[u].c * z[u][1];
+          s1 += B[u].b * z[u][0] + B[u].d * z[u][1];
+        }
+      }
+      for (; j < n; j += E) {
         const int k = cols[2 * (r.w + j)], mp = cols[2 * (r.w + j) + 1];
         const Blk<T> B = ld_blk(c.lu + sB<S>(mp, s));
         const T z0 = c.y[sP<S>(k, s)], z1 = c.y[sP<S>(k, s) + 1];
@@ -1520,13 +1657,12 @@ __device__ __forceinline__ void phase_tsolve(const AdjSym& a, const Dims& D, St<
       s1 = group_sum<T, S>(s1, G);
       if (e == 0) {
         if (UT) {
-          const Blk<T> Di = ld_blk(c.dinv + sB<S>(row, s));
-          const T t0 = c.y[sP<S>(row, s)] - s0, t1 = c.y[sP<S>(row, s) + 1] - s1;
+          const T t0 = ya0 - s0, t1 = ya1 - s1;
           c.y[sP<S>(row, s)] = Di.a * t0 + Di.c * t1;
           c.y[sP<S>(row, s) + 1] = Di.b * t0 + Di.d * t1;
         } else {
-          c.y[sP<S>(row, s)] -= s0;
-          c.y[sP<S>(row, s) + 1] -= s1;
+          c.y[sP<S>(row, s)] = ya0 - s0;
+          c.y[sP<S>(row, s) + 1] = ya1 - s1;
         }
       }
     }
@@ -1614,39 +1750,59 @@ __device__ __forceinline__ void phase_adj_residual_s(const Sym& m, const Dims& D
                                                      const double* lam, double* g, bool to_y,
                                                      GenW gw = GenW{}) {
   for (int idx = tid; idx < D.n_bus * S; idx += nt) {   // w_i = nu_i conj(V_i)
-    const int i = idx / S, s = idx % S;
+    const int i = idx / S, s = idx % S, o = c.g(i, s);
     const int a = m.bus_blk[i];
     double nr = 0.0, ni = 0.0;
     if (a >= 0 && lam) { nr = lam[sP<S>(a, s)]; ni = m.bus_type[i] == 0 ? lam[sP<S>(a, s) + 1] : 0.0; }
     gw.add(i, s, m.bus_type[i], nr, ni);
-    c.dvr[idx] = nr * c.e[idx] + ni * c.f[idx];
-    c.dvi[idx] = ni * c.e[idx] - nr * c.f[idx];
+    const double e = c.e[o], f = c.f[o];
+    c.dvr[o] = nr * e + ni * f;
+    c.dvi[o] = ni * e - nr * f;
   }
   __syncthreads();
   for (int idx = tid; idx < D.n_bus * S; idx += nt) {
-    const int mb = idx / S, s = idx % S;
+    const int mb = idx / S, s = idx % S, o = c.g(mb, s);
+    // sum over the row's entries of Y_im w_i, four entries per round with
+    // their loads issued together, in column order
     double tr = 0.0, ti = 0.0;
-    for (int q = m.y_rp[mb]; q < m.y_rp[mb + 1]; ++q) {
-      const int i = sI<S>(m.y_ci[q], s);
-      const int qt = m.y_tr[q];              // position of Y_im
-      const double yg = m.y_g[qt], yb = m.y_b[qt];
-      tr += yg * c.dvr[i] - yb * c.dvi[i];
-      ti += yg * c.dvi[i] + yb * c.dvr[i];
+    const int q1 = m.y_rp[mb + 1];
+    for (int q = m.y_rp[mb]; q < q1; q += 4) {
+      int j[4];
+      double yg[4], yb[4], wr[4], wi[4];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const bool in = q + w < q1;
+        j[w] = in ? m.y_ci[q + w] : 0;
+        const int qt = in ? m.y_tr[q + w] : 0;   // position of Y_im
+        yg[w] = in ? m.y_g[qt] : 0.0;
+        yb[w] = in ? m.y_b[qt] : 0.0;
+      }
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        wr[w] = c.dvr[c.g(j[w], s)];
+        wi[w] = c.dvi[c.g(j[w], s)];
+      }
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+        if (q + w < q1) {
+          tr += yg[w] * wr[w] - yb[w] * wi[w];
+          ti += yg[w] * wi[w] + yb[w] * wr[w];
+        }
     }
     const int a = m.bus_blk[mb];
     double nr = 0.0, ni = 0.0;
     if (a >= 0 && lam) { nr = lam[sP<S>(a, s)]; ni = m.bus_type[mb] == 0 ? lam[sP<S>(a, s) + 1] : 0.0; }
     gw.add(mb, s, m.bus_type[mb], nr, ni);
-    const double ir = c.ire[idx], ii = c.iim[idx];
+    const double ir = c.ire[o], ii = c.iim[o];
     const double cr = (nr * ir - ni * ii) + tr;      // Re c_m
     const double ci = -(nr * ii + ni * ir) + ti;     // Im c_m
-    const double e = c.e[idx], f = c.f[idx];
+    const double e = c.e[o], f = c.f[o], vm = c.vm[o];
     const double vcr = e * cr - f * ci;               // Re(V_m c_m)
     const double vci = e * ci + f * cr;               // Im(V_m c_m)
-    c.aux[idx] = vcr / c.vm[idx];
+    c.aux[idx] = vcr / vm;
     if (a >= 0 && g) {
       const double r0 = g[sP<S>(a, s)] - vci;
-      const double r1 = m.bus_type[mb] == 0 ? g[sP<S>(a, s) + 1] + vcr / c.vm[idx] : 0.0;
+      const double r1 = m.bus_type[mb] == 0 ? g[sP<S>(a, s) + 1] + vcr / vm : 0.0;
       if (to_y) { c.y[sP<S>(a, s)] = T(r0); c.y[sP<S>(a, s) + 1] = T(r1); }
       else { g[sP<S>(a, s)] = r0; g[sP<S>(a, s) + 1] = r1; }   // in place
     }
@@ -1691,13 +1847,14 @@ __global__ void __launch_bounds__(RES ? kResThreads : 512) k_adjoint_slice(KPara
     double e = 1.0, f = 0.0, v = 1.0;
     if (b < kp.count) {
       const double* gd = kp.ws_d + (size_t)b * kp.lay.sd;
-      e = gd[kp.lay.o_e + i];
-      f = gd[kp.lay.o_f + i];
-      v = gd[kp.lay.o_vm + i];
+      const int gi = i * kp.lay.gk;
+      e = gd[kp.lay.o_e + gi];
+      f = gd[kp.lay.o_f + gi];
+      v = gd[kp.lay.o_vm + gi];
     }
-    c.e[idx] = e;
-    c.f[idx] = f;
-    c.vm[idx] = v;
+    c.e[c.g(i, s)] = e;
+    c.f[c.g(i, s)] = f;
+    c.vm[c.g(i, s)] = v;
   }
   for (int q = tid; q < 4 * D.nnzb * S; q += nt) {
     const int comp = q & 3, blk = q >> 2, p = blk / S, s = blk % S;
@@ -1721,14 +1878,12 @@ __global__ void __launch_bounds__(RES ? kResThreads : 512) k_adjoint_slice(KPara
   for (int idx = tid; idx < n * S; idx += nt) {
     const int i = idx / S, s = idx % S;
     const int b = slice * S + s;
-    double ir = 0.0, ii = 0.0;
-    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
-      const int j = sI<S>(m.y_ci[q], s);
-      ir += m.y_g[q] * c.e[j] - m.y_b[q] * c.f[j];
-      ii += m.y_g[q] * c.f[j] + m.y_b[q] * c.e[j];
-    }
-    c.ire[idx] = ir;
-    c.iim[idx] = ii;
+    double ir[1], ii[1];
+    const int ib[1] = {i};
+    const bool vb[1] = {true};
+    yrow_multi<S, 1, 4>(m, c.e, c.f, c.gs, ib, s, vb, ir, ii);
+    c.ire[c.g(i, s)] = ir[0];
+    c.iim[c.g(i, s)] = ii[0];
     const int a = m.bus_blk[i];
     if (a < 0) continue;
     double g0 = 0.0, g1 = 0.0;
@@ -1860,22 +2015,23 @@ __global__ void __launch_bounds__(256) k_jacobian_dense(KParams kp) {
   double* gd = kp.ws_d + (size_t)b * kp.lay.sd;
   double *e = gd + kp.lay.o_e, *f = gd + kp.lay.o_f, *vm = gd + kp.lay.o_vm;
   double *ire = gd + kp.lay.o_ire, *iim = gd + kp.lay.o_iim;
+  const int gk = kp.lay.gk;   // the workspace groups a bus's values: element i at i * gk
   for (int i = tid; i < n; i += nt) {
-    vm[i] = kp.vm_in[io + i];
+    vm[i * gk] = kp.vm_in[io + i];
     const double va = m.bus_type[i] == 2 ? 0.0 : kp.va_in[io + i];
-    e[i] = vm[i] * cos(va);
-    f[i] = vm[i] * sin(va);
+    e[i * gk] = vm[i * gk] * cos(va);
+    f[i * gk] = vm[i * gk] * sin(va);
   }
   __syncthreads();
   for (int i = tid; i < n; i += nt) {
     double ir = 0.0, ii = 0.0;
     for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
       const int j = m.y_ci[q];
-      ir += m.y_g[q] * e[j] - m.y_b[q] * f[j];
-      ii += m.y_g[q] * f[j] + m.y_b[q] * e[j];
+      ir += m.y_g[q] * e[j * gk] - m.y_b[q] * f[j * gk];
+      ii += m.y_g[q] * f[j * gk] + m.y_b[q] * e[j * gk];
     }
-    ire[i] = ir;
-    iim[i] = ii;
+    ire[i * gk] = ir;
+    iim[i * gk] = ii;
   }
   __syncthreads();
   double* o = kp.out + (size_t)b * nj * nj;
@@ -1888,8 +2044,8 @@ __global__ void __launch_bounds__(256) k_jacobian_dense(KParams kp) {
     for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
       const int j = m.y_ci[q];
       if (m.bus_type[j] == 2) continue;
-      const J4 x = (i == j) ? jac_diag(m.y_g[q], m.y_b[q], e[i], f[i], vm[i], 1.0 / vm[i], ire[i], iim[i])
-                            : jac_off(m.y_g[q], m.y_b[q], e[i], f[i], e[j], f[j], 1.0 / vm[j]);
+      const J4 x = (i == j) ? jac_diag(m.y_g[q], m.y_b[q], e[i * gk], f[i * gk], vm[i * gk], 1.0 / vm[i * gk], ire[i * gk], iim[i * gk])
+                            : jac_off(m.y_g[q], m.y_b[q], e[i * gk], f[i * gk], e[j * gk], f[j * gk], 1.0 / vm[j * gk]);
       const int cT = D.npq + m.ord_p[j];
       const int cV = m.bus_type[j] == 0 ? m.ord_q[j] : -1;
       o[(size_t)rP * nj + cT] = x.v[0];
