@@ -811,20 +811,46 @@ template <typename T, int S>
 __device__ __forceinline__ void ltail_fsolve(const Sym& m, const Dims& D, St<T>& c, const T* tl, int tid, int nt) {
   const int t = D.tail_t, tb = D.tail_base;
   const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
+  // the terms of the tail rows on rows outside the tail (their L blocks left
+  // of the tail, against unknowns already solved): with at most 32 tail rows
+  // lanes l and l + 32 split row l's entries, four in flight per lane, and
+  // the two partial sums meet by a lane swap
+  const bool split = t <= 32;
+  const int lr = split ? (l & 31) : l, hs = split ? (l >> 5) : 0, step = split ? 2 : 1;
   for (int s = w; s < S; s += nw) {
-    T y0 = T(0), y1 = T(0);
-    if (l < t) {
-      const int a = tb + l;
-      y0 = c.y[sP<S>(a, s)];
-      y1 = c.y[sP<S>(a, s) + 1];
-      for (int p = m.rp[a]; p < m.tail_split[l]; ++p) {
-        const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
-        const int k = m.ci[p];
-        const T z0 = c.y[sP<S>(k, s)], z1 = c.y[sP<S>(k, s) + 1];
-        y0 -= L.a * z0 + L.b * z1;
-        y1 -= L.c * z0 + L.d * z1;
+    T y0 = T(0), y1 = T(0), o0 = T(0), o1 = T(0);
+    if (lr < t) {
+      const int a = tb + lr;
+      if (hs == 0) {
+        y0 = c.y[sP<S>(a, s)];
+        y1 = c.y[sP<S>(a, s) + 1];
+      }
+      const int p1 = m.tail_split[lr];
+      for (int p = m.rp[a] + hs; p < p1; p += 4 * step) {
+        Blk<T> L[4];
+        T z[4][2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int pu = p + u * step;
+          const bool in = pu < p1;
+          const int k = in ? m.ci[pu] : 0;
+          L[u] = in ? ld_blk(c.lu + sB<S>(pu, s)) : Blk<T>{T(0), T(0), T(0), T(0)};
+          z[u][0] = c.y[sP<S>(k, s)];
+          z[u][1] = c.y[sP<S>(k, s) + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          o0 += L[u].a * z[u][0] + L[u].b * z[u][1];
+          o1 += L[u].c * z[u][0] + L[u].d * z[u][1];
+        }
       }
     }
+    if (split) {
+      o0 += __shfl_xor(o0, 32);
+      o1 += __shfl_xor(o1, 32);
+    }
+    y0 -= o0;
+    y1 -= o1;
     for (int j = 0; j < t; ++j) {
       const T yj0 = lane_bcast(y0, j), yj1 = lane_bcast(y1, j);
       if (l > j && l < t) {
@@ -1707,11 +1733,25 @@ __device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const D
   if (l < t) {
     const int row = tb + l;
     y = c.y[sP<S>(row, s) + h];
-    for (int q = a.tt_ptr[l]; q < a.tt_ptr[l + 1]; ++q) {
-      const int k = a.tt_pairs[2 * q], mp = a.tt_pairs[2 * q + 1];
-      const T* b = c.lu + sB<S>(mp, s);
-      y -= b[h] * c.y[sP<S>(k, s)] + b[2 + h] * c.y[sP<S>(k, s) + 1];
+    // the terms on rows outside the tail, four pairs in flight
+    const int q1 = a.tt_ptr[l + 1];
+    T acc = T(0);
+    for (int q = a.tt_ptr[l]; q < q1; q += 4) {
+      T b0[4], b1[4], z0[4], z1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool in = q + u < q1;
+        const int k = in ? a.tt_pairs[2 * (q + u)] : 0, mp = in ? a.tt_pairs[2 * (q + u) + 1] : 0;
+        const T* b = c.lu + sB<S>(mp, s);
+        b0[u] = in ? b[h] : T(0);
+        b1[u] = in ? b[2 + h] : T(0);
+        z0[u] = c.y[sP<S>(k, s)];
+        z1[u] = c.y[sP<S>(k, s) + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += b0[u] * z0[u] + b1[u] * z1[u];
     }
+    y -= acc;
   }
   const unsigned lm = __builtin_amdgcn_readfirstlane(m.tail_mask[t]);
   const unsigned cm = __builtin_amdgcn_readfirstlane(m.tail_mask[t + 1]);
