@@ -432,8 +432,12 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   // 2048 words of staged metadata; the chunk budget takes what remains.
   // S = 1 always fits: the tail holds at most 32 x 32 blocks.
   const int n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  // the LDS copy of the tail: per scenario its tail-column blocks (stride
+  // odd, so that the scenarios' copies start in different banks), pivot
+  // inverses and right-hand sides, then the tail program's solve prefix
+  const size_t tail_nbs = S.tail_cblk.size() | 1;
   auto tail_bytes = [&](int sl) {
-    return (size_t)sl * tsz * (4 * S.tail_cblk.size() + 6 * (size_t)S.tail_t);
+    return (size_t)sl * tsz * (4 * tail_nbs + 6 * (size_t)S.tail_t) + 4 * (size_t)S.tail_prog_prefix;
   };
   int hbm_slice = 1;
   while (hbm_slice < sable::kMaxSlice && batch / (2 * hbm_slice) >= n_cu) hbm_slice *= 2;
@@ -464,8 +468,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   so.adj_bytes = (int)pk.align();
   so.tail_cblk = (int)pk.add(S.tail_cblk); so.tail_lbase = (int)pk.add(S.tail_lbase);
   so.tail_cpos = (int)pk.add(S.tail_cpos);
-  so.upd_tgt = (int)pk.add(S.upd_tgt);
-  so.tk_ptr = (int)pk.add(S.tk_ptr); so.tstep4 = (int)pk.add(S.tstep4);
+  so.tail_prog = (int)pk.add(S.tail_prog);
   so.ord_p = (int)pk.add(ord_p); so.ord_q = (int)pk.add(ord_q);
   so.total_bytes = (int)pk.align();
   sable::Dims& dm = t->dims;
@@ -477,7 +480,15 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   dm.nch_f = (int)chunks.f_ptr.size() - 1;
   dm.nch_fs = (int)chunks.fs_ptr.size() - 1;
   dm.nch_bs = (int)chunks.bs_ptr.size() - 1;
-  dm.chunk_ints = chunks.max_ints;
+  // the LDS copy of the tail reads its elimination program from the
+  // metadata area (free while the tail is factored) when the area, grown
+  // within the room left, holds it
+  dm.tail_nbs = (int)tail_nbs;
+  dm.tail_prog_ints = (int)S.tail_prog.size();
+  dm.tail_prog_prefix = S.tail_prog_prefix;
+  const size_t upd_words = S.tail_prog.size() - (size_t)S.tail_prog_prefix;
+  dm.tail_prog_lds = upd_words <= room ? 1 : 0;
+  dm.chunk_ints = std::max<int>(chunks.max_ints, dm.tail_prog_lds ? (int)(upd_words + 3) / 4 * 4 : 0);
   dm.tail_nblk = (int)S.tail_cblk.size();
   dm.nch_ut = (int)chunks.ut_ptr.size() - 1;
   dm.nch_lt = (int)chunks.lt_ptr.size() - 1;
@@ -530,7 +541,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     const int sl = hbm_slice;
     t->slice = sl;
     t->lay = make_layout(S.n_bus, S.nb, S.nnzb(), sl > 1);
-    t->lds_bytes = sable::kScratchBytes + 4 * (size_t)chunks.max_ints + tail_bytes(sl);
+    t->lds_bytes = sable::kScratchBytes + 4 * (size_t)dm.chunk_ints + tail_bytes(sl);
     // the adjoint reads this slice workspace in place
     t->adj_slice = -sl;
     t->adj_nt = std::min(512, std::max(256, 64 * sl));

@@ -71,7 +71,7 @@ struct SymOffsets {
   int ut_ptr, ut_blob, lt_ptr, lt_blob, tt_ptr, tt_pairs, y_tr;
   int adj_bytes;
   int tail_cblk, tail_lbase, tail_cpos;   // compact tail numbering (LDS copy of the tail)
-  int upd_tgt, tk_ptr, tstep4;            // per-pivot step lists of the tail (LDS tail copy)
+  int tail_prog;                          // per-pivot elimination program of the tail (LDS tail copy)
   int ord_p, ord_q;                       // paper-order positions (exports)
   int total_bytes;
 };
@@ -85,6 +85,10 @@ struct Dims {
   int nch_ut, nch_lt;             // metadata chunks of the transposed solves
   int chunk_ints;                 // largest chunk (int32 words), staged after the LDS scratch
   int tail_nblk;                  // blocks of the tail rows in tail columns (LDS tail copy)
+  int tail_nbs;                  // stride of a scenario's blocks in the LDS tail copy (odd)
+  int tail_prog_ints;             // words of the tail program
+  int tail_prog_prefix;           // its records, step and column words: kept in LDS
+  int tail_prog_lds;              // 1: its update words staged in the metadata area, 0: read in place
 };
 
 // Offsets of the per-scenario arrays, in elements.  FP64 arrays:

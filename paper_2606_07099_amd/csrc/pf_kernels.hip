@@ -97,9 +97,7 @@ struct Sym {
   const double *y_g, *y_b;
   const int *rp, *ci, *diag;
   const int4* fill4;
-  const int* upd_tgt;
-  const int *tail_pos, *tail_split, *tk_ptr;
-  const int4* tstep4;
+  const int *tail_pos, *tail_split, *tail_prog;
   const unsigned* tail_mask;
   const int *y_tr, *ord_p, *ord_q;
   const int *f_ptr, *f_blob, *fs_ptr, *fs_blob, *bs_ptr, *bs_blob;
@@ -129,9 +127,7 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
   m.fs_blob = I(nb, o.fs_blob);
   m.bs_ptr = I(nb, o.bs_ptr);
   m.bs_blob = I(nb, o.bs_blob);
-  m.upd_tgt = I(g, o.upd_tgt);
-  m.tk_ptr = I(g, o.tk_ptr);
-  m.tstep4 = reinterpret_cast<const int4*>(g + o.tstep4);
+  m.tail_prog = I(g, o.tail_prog);
   m.y_tr = I(g, o.y_tr);   // LDS-resident adjoint slices rebind it to their LDS copy
   m.ord_p = I(g, o.ord_p);
   m.ord_q = I(g, o.ord_q);
@@ -712,201 +708,285 @@ __device__ __forceinline__ float lane_bcast(float v, int l) {
 
 // ----------------------------------------------------------------------------
 // the tail of HBM-resident slices in an LDS copy: its tail-column blocks in a
-// compact numbering (tl, interleaved by scenario) and its pivot inverses (td)
-// are copied in after the barrier-synchronised part of the factorisation,
-// factored and solved there by the same per-pivot elimination, one
-// wavefront per scenario, and written back only when the factors are kept
+// compact numbering (tl), its pivot inverses (td) and right-hand sides (ty),
+// each scenario's copy contiguous so that the lanes of the wavefront that
+// works on it read different banks.  The blocks are copied in after the
+// barrier-synchronised part of the factorisation, factored and solved there
+// one wavefront per scenario, and written back only when the factors are
+// kept.  The tail program (records of every pivot row: its pivot block,
+// masks of its blocks left and right of the diagonal, the rows below it)
+// stays in LDS (tq) for the whole launch; the factorisation's update words
+// are staged in the metadata area or read in place (tp).
+
+__device__ __forceinline__ int tcB(int cb, int s, int nbs) { return (s * nbs + cb) * 4; }
+__device__ __forceinline__ int tdB(int k, int s, int t) { return (s * t + k) * 4; }
+__device__ __forceinline__ int tyP(int k, int s, int t) { return (s * t + k) * 2; }
 
 template <typename T, int S>
 __device__ __forceinline__ void ltail_copy(const Sym& m, const Dims& D, St<T>& c, T* tl, int tid, int nt,
                                            bool out) {
   const int nq = D.tail_nblk * S * 4;
   for (int q = tid; q < nq; q += nt) {
-    const int comp = q & 3, blk = q >> 2, cb = blk / S, s = blk % S;
+    const int comp = q & 3, s = (q >> 2) % S, cb = (q >> 2) / S;
     T* g = c.lu + sB<S>(m.tail_cblk[cb], s) + comp;
-    if (out) *g = tl[q];
-    else tl[q] = *g;
+    T* x = tl + tcB(cb, s, D.tail_nbs) + comp;
+    if (out) *g = *x;
+    else *x = *g;
   }
 }
 
 template <typename T, int S>
 __device__ __forceinline__ void ltail_store_dinv(const Dims& D, St<T>& c, const T* td, int tid, int nt) {
-  for (int q = tid; q < D.tail_t * S * 4; q += nt) c.dinv[sB<S>(D.tail_base, 0) + q] = td[q];
+  for (int q = tid; q < D.tail_t * S * 4; q += nt) {
+    const int comp = q & 3, s = (q >> 2) % S, k = (q >> 2) / S;
+    c.dinv[sB<S>(D.tail_base + k, s) + comp] = td[tdB(k, s, D.tail_t) + comp];
+  }
 }
 
-// ty: LDS copy of the tail rows' right-hand sides for the fused forward
-// solve (t x 2 per scenario), written back at the end
+// ty: the tail rows' right-hand sides for the fused forward solve, written
+// back at the end.  Every lane inverts the pivot block itself from its LDS
+// copy (a broadcast read); the updates of one pivot have distinct targets
+// outside its row and column, so the lanes take them two at a time with
+// every load issued first; the rows' multipliers L(i, k) D_k^-1 replace
+// their blocks only after all updates have read them.
 template <typename T, int S>
-__device__ __forceinline__ void ltail_factor(const Sym& m, const Dims& D, St<T>& c, T* tl, T* td, T* ty, int tid,
-                                             int nt, bool fwd, int* piv) {
-  const int t = D.tail_t, tb = D.tail_base;
+__device__ __forceinline__ void ltail_factor(const Dims& D, St<T>& c, T* tl, T* td, T* ty, const int* tq,
+                                             const int* tp, int tid, int nt, bool fwd, int* piv) {
+  const int t = D.tail_t, tb = D.tail_base, nbs = D.tail_nbs;
   const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
   for (int s = w; s < S; s += nw) {
     if (fwd && l < t) {
-      ty[sP<S>(l, s)] = c.y[sP<S>(tb + l, s)];
-      ty[sP<S>(l, s) + 1] = c.y[sP<S>(tb + l, s) + 1];
+      ty[tyP(l, s, t)] = c.y[sP<S>(tb + l, s)];
+      ty[tyP(l, s, t) + 1] = c.y[sP<S>(tb + l, s) + 1];
     }
+    asm volatile("" ::: "memory");
     for (int k = 0; k < t; ++k) {
-      const int ak = tb + k;
-      const int lb = m.tail_lbase[k] - m.rp[ak];   // compact index = position + lb on row ak
-      const int dk = m.diag[ak] + lb;
-      Blk<T> Di = {T(0), T(0), T(0), T(0)};
+      const int4 r = reinterpret_cast<const int4*>(tq)[2 * k];   // pivot, first U, nu | ns << 16, steps
+      const int uoff = tq[8 * k + 4];
+      const Blk<T> Dk = ld_blk(tl + tcB(r.x, s, nbs));
+      const T det = Dk.a * Dk.d - Dk.b * Dk.c;
+      const T inv = recip(det);
+      const Blk<T> Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
       if (l == 0) {
-        const Blk<T> Dk = ld_blk(tl + sB<S>(dk, s));
-        const T det = Dk.a * Dk.d - Dk.b * Dk.c;
-        const T inv = recip(det);
-        Di = {Dk.d * inv, -Dk.b * inv, -Dk.c * inv, Dk.a * inv};
         // pivots of the block: a, then the Schur complement d - c b / a
         const T eps = sizeof(T) == 8 ? T(1e-14) : T(1e-7);
         const bool zero = !(fabs(Dk.a) > eps * (fabs(Dk.a) + fabs(Dk.b))) ||
                           !(fabs(det) > eps * fabs(Dk.a) * (fabs(Dk.c) + fabs(Dk.d))) ||
                           !isfinite(inv);
         if (zero) piv[s] = 1;
-        st_blk(td + sB<S>(k, s), Di);
+        st_blk(td + tdB(k, s, t), Di);
       }
-      Di = {lane_bcast(Di.a, 0), lane_bcast(Di.b, 0), lane_bcast(Di.c, 0), lane_bcast(Di.d, 0)};
-      const int t0 = m.tk_ptr[k], t1 = m.tk_ptr[k + 1];
-      if (t1 > t0) {
-        T yk0 = T(0), yk1 = T(0);
-        if (fwd) { yk0 = ty[sP<S>(k, s)]; yk1 = ty[sP<S>(k, s) + 1]; }
-        const int ks = m.diag[ak] + 1 + lb, n = m.rp[ak + 1] - m.diag[ak] - 1;
-        int E = 1;
-        while (E < n && E < 64) E <<= 1;
-        const int lg = __builtin_ctz(E), per = 64 >> lg;
-        const int e = l & (E - 1);
-        for (int st = t0 + (l >> lg); st - (l >> lg) < t1; st += per) {
-          if (st >= t1) continue;
-          const int4 r = m.tstep4[st];   // row i, q, first target, -
-          const int wb = m.tail_lbase[r.x - tb];   // compact index of row-relative offset 0
-          const Blk<T> L = mul(ld_blk(tl + sB<S>(wb + r.y, s)), Di);
-          for (int j = e; j < n; j += E) {
-            const Blk<T> U = ld_blk(tl + sB<S>(ks + j, s));
-            T* a = tl + sB<S>(wb + m.upd_tgt[r.z + j], s);
-            Blk<T> x = ld_blk(a);
-            const Blk<T> LU = mul(L, U);
-            x.a -= LU.a; x.b -= LU.b; x.c -= LU.c; x.d -= LU.d;
-            st_blk(a, x);
-          }
-          if (e == 0) {
-            st_blk(tl + sB<S>(wb + r.y, s), L);
-            if (fwd) {
-              ty[sP<S>(r.x - tb, s)] -= L.a * yk0 + L.b * yk1;
-              ty[sP<S>(r.x - tb, s) + 1] -= L.c * yk0 + L.d * yk1;
-            }
-          }
+      const int nu = r.z & 0xffff, ns = r.z >> 16;
+      const unsigned* up = reinterpret_cast<const unsigned*>(tp + (uoff - D.tail_prog_prefix));
+      const int np = nu * ns;
+      for (int q = l; q < np; q += 128) {
+        const bool two = q + 64 < np;
+        const unsigned r0 = up[q], r1 = two ? up[q + 64] : r0;
+        T* a0 = tl + tcB((int)(r0 & 2047u), s, nbs);
+        T* a1 = tl + tcB((int)(r1 & 2047u), s, nbs);
+        const Blk<T> L0 = ld_blk(tl + tcB((int)((r0 >> 11) & 2047u), s, nbs));
+        const Blk<T> U0 = ld_blk(tl + tcB(r.y + (int)(r0 >> 22), s, nbs));
+        const Blk<T> L1 = ld_blk(tl + tcB((int)((r1 >> 11) & 2047u), s, nbs));
+        const Blk<T> U1 = ld_blk(tl + tcB(r.y + (int)(r1 >> 22), s, nbs));
+        Blk<T> x0 = ld_blk(a0), x1 = ld_blk(a1);
+        const Blk<T> M0 = mul(mul(L0, Di), U0), M1 = mul(mul(L1, Di), U1);
+        x0.a -= M0.a; x0.b -= M0.b; x0.c -= M0.c; x0.d -= M0.d;
+        x1.a -= M1.a; x1.b -= M1.b; x1.c -= M1.c; x1.d -= M1.d;
+        st_blk(a0, x0);
+        if (two) st_blk(a1, x1);
+      }
+      asm volatile("" ::: "memory");
+      if (l < ns) {
+        const int sw = tq[r.w + l], lc = sw & 0xffff, ir = sw >> 16;
+        const Blk<T> L = mul(ld_blk(tl + tcB(lc, s, nbs)), Di);
+        st_blk(tl + tcB(lc, s, nbs), L);
+        if (fwd) {
+          const T yk0 = ty[tyP(k, s, t)], yk1 = ty[tyP(k, s, t) + 1];
+          ty[tyP(ir, s, t)] -= L.a * yk0 + L.b * yk1;
+          ty[tyP(ir, s, t) + 1] -= L.c * yk0 + L.d * yk1;
         }
       }
-      // the next pivot reads what this one updated: LDS operations of a
+      // the next pivot reads what this one wrote: LDS operations of a
       // wavefront complete in order, so only the compiler must keep it
       asm volatile("" ::: "memory");
     }
     if (fwd && l < t) {
-      c.y[sP<S>(tb + l, s)] = ty[sP<S>(l, s)];
-      c.y[sP<S>(tb + l, s) + 1] = ty[sP<S>(l, s) + 1];
+      c.y[sP<S>(tb + l, s)] = ty[tyP(l, s, t)];
+      c.y[sP<S>(tb + l, s) + 1] = ty[tyP(l, s, t) + 1];
     }
   }
 }
 
+// stages the tail program's update words into the metadata area (when they
+// fit there); returns where the factorisation reads them
+__device__ __forceinline__ const int* ltail_updates(const Sym& m, const Dims& D, unsigned char* stg, int tid,
+                                                    int nt) {
+  const int* src = m.tail_prog + D.tail_prog_prefix;
+  if (!D.tail_prog_lds) return src;
+  int* dst = reinterpret_cast<int*>(stg);
+  for (int q = tid; q < D.tail_prog_ints - D.tail_prog_prefix; q += nt) dst[q] = src[q];
+  return dst;
+}
+
+// the triangular solves of the tail: lane l < t holds the right-hand side
+// of tail row l in registers, solved values reach the other lanes by lane
+// broadcast, and each lane walks its own row's blocks (consecutive compact
+// indices located by the row's masks) with the next two loaded ahead of use
+
+// forward solve of scenario s's tail rows (lanes l and l + 32 share row l
+// for the terms on rows outside the tail: their L blocks left of the tail,
+// against unknowns already solved, four in flight per lane, the two partial
+// sums meeting by a lane swap); the result stays in y0, y1
 template <typename T, int S>
-__device__ __forceinline__ void ltail_fsolve(const Sym& m, const Dims& D, St<T>& c, const T* tl, int tid, int nt) {
-  const int t = D.tail_t, tb = D.tail_base;
-  const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
-  // the terms of the tail rows on rows outside the tail (their L blocks left
-  // of the tail, against unknowns already solved): with at most 32 tail rows
-  // lanes l and l + 32 split row l's entries, four in flight per lane, and
-  // the two partial sums meet by a lane swap
-  const bool split = t <= 32;
-  const int lr = split ? (l & 31) : l, hs = split ? (l >> 5) : 0, step = split ? 2 : 1;
-  for (int s = w; s < S; s += nw) {
-    T y0 = T(0), y1 = T(0), o0 = T(0), o1 = T(0);
-    if (lr < t) {
-      const int a = tb + lr;
-      if (hs == 0) {
-        y0 = c.y[sP<S>(a, s)];
-        y1 = c.y[sP<S>(a, s) + 1];
-      }
-      const int p1 = m.tail_split[lr];
-      for (int p = m.rp[a] + hs; p < p1; p += 4 * step) {
-        Blk<T> L[4];
-        T z[4][2];
+__device__ __forceinline__ void ltail_fs_one(const Sym& m, const Dims& D, St<T>& c, const T* tl, const int* tq,
+                                             int s, int l, T& y0, T& y1) {
+  const int t = D.tail_t, tb = D.tail_base, nbs = D.tail_nbs;
+  const int lr = l & 31, hs = l >> 5;
+  T o0 = T(0), o1 = T(0);
+  y0 = T(0);
+  y1 = T(0);
+  if (lr < t) {
+    const int a = tb + lr;
+    if (hs == 0) {
+      y0 = c.y[sP<S>(a, s)];
+      y1 = c.y[sP<S>(a, s) + 1];
+    }
+    const int p1 = m.tail_split[lr];
+    for (int p = m.rp[a] + hs; p < p1; p += 8) {
+      Blk<T> L[4];
+      T z[4][2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int pu = p + u * step;
-          const bool in = pu < p1;
-          const int k = in ? m.ci[pu] : 0;
-          L[u] = in ? ld_blk(c.lu + sB<S>(pu, s)) : Blk<T>{T(0), T(0), T(0), T(0)};
-          z[u][0] = c.y[sP<S>(k, s)];
-          z[u][1] = c.y[sP<S>(k, s) + 1];
-        }
+      for (int u = 0; u < 4; ++u) {
+        const int pu = p + 2 * u;
+        const bool in = pu < p1;
+        const int k = in ? m.ci[pu] : 0;
+        L[u] = in ? ld_blk(c.lu + sB<S>(pu, s)) : Blk<T>{T(0), T(0), T(0), T(0)};
+        z[u][0] = c.y[sP<S>(k, s)];
+        z[u][1] = c.y[sP<S>(k, s) + 1];
+      }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          o0 += L[u].a * z[u][0] + L[u].b * z[u][1];
-          o1 += L[u].c * z[u][0] + L[u].d * z[u][1];
-        }
+      for (int u = 0; u < 4; ++u) {
+        o0 += L[u].a * z[u][0] + L[u].b * z[u][1];
+        o1 += L[u].c * z[u][0] + L[u].d * z[u][1];
       }
     }
-    if (split) {
-      o0 += __shfl_xor(o0, 32);
-      o1 += __shfl_xor(o1, 32);
+  }
+  o0 += __shfl_xor(o0, 32);
+  o1 += __shfl_xor(o1, 32);
+  y0 -= o0;
+  y1 -= o1;
+  unsigned mk = l < t ? (unsigned)tq[8 * l + 5] : 0u;
+  int idx = l < t ? tq[8 * l] - __popc(mk) : 0;   // the row's first block left of the diagonal
+  const Blk<T> Z = {T(0), T(0), T(0), T(0)};
+  Blk<T> L0 = mk ? ld_blk(tl + tcB(idx, s, nbs)) : Z;
+  Blk<T> L1 = (mk & (mk - 1)) ? ld_blk(tl + tcB(idx + 1, s, nbs)) : Z;
+  for (int k = 0; k + 1 < t; ++k) {
+    const T yk0 = lane_bcast(y0, k), yk1 = lane_bcast(y1, k);
+    if (mk & (1u << k)) {   // k is the lowest column left to do
+      y0 -= L0.a * yk0 + L0.b * yk1;
+      y1 -= L0.c * yk0 + L0.d * yk1;
+      mk &= mk - 1;
+      ++idx;
+      L0 = L1;
+      if (mk & (mk - 1)) L1 = ld_blk(tl + tcB(idx + 1, s, nbs));
     }
-    y0 -= o0;
-    y1 -= o1;
-    for (int j = 0; j < t; ++j) {
-      const T yj0 = lane_bcast(y0, j), yj1 = lane_bcast(y1, j);
-      if (l > j && l < t) {
-        const int p = m.tail_cpos[l * t + j];
-        if (p >= 0) {
-          const Blk<T> L = ld_blk(tl + sB<S>(p, s));
-          y0 -= L.a * yj0 + L.b * yj1;
-          y1 -= L.c * yj0 + L.d * yj1;
-        }
-      }
+  }
+}
+
+// backward solve of scenario s's tail rows, right-hand sides in y0, y1
+template <typename T, int S>
+__device__ __forceinline__ void ltail_bs_one(const Dims& D, const T* tl, const T* td, const int* tq, int s,
+                                             int l, T& y0, T& y1) {
+  const int t = D.tail_t, nbs = D.tail_nbs;
+  const Blk<T> Z = {T(0), T(0), T(0), T(0)};
+  Blk<T> Di = Z;
+  unsigned mk = 0u;
+  int idx = 0;
+  if (l < t) {
+    Di = ld_blk(td + tdB(l, s, t));
+    mk = (unsigned)tq[8 * l + 6];
+    idx = tq[8 * l] + __popc(mk);   // the row's last block right of the diagonal
+  }
+  Blk<T> U0 = mk ? ld_blk(tl + tcB(idx, s, nbs)) : Z;
+  Blk<T> U1 = (mk & (mk - 1)) ? ld_blk(tl + tcB(idx - 1, s, nbs)) : Z;
+  for (int j = t - 1; j >= 0; --j) {
+    if (l == j) {
+      const T x0 = Di.a * y0 + Di.b * y1, x1 = Di.c * y0 + Di.d * y1;
+      y0 = x0;
+      y1 = x1;
     }
-    if (l < t) { c.y[sP<S>(tb + l, s)] = y0; c.y[sP<S>(tb + l, s) + 1] = y1; }
+    if (j == 0) break;
+    const T xj0 = lane_bcast(y0, j), xj1 = lane_bcast(y1, j);
+    if (mk & (1u << j)) {   // j is the highest column left to do
+      y0 -= U0.a * xj0 + U0.b * xj1;
+      y1 -= U0.c * xj0 + U0.d * xj1;
+      mk &= ~(1u << j);
+      --idx;
+      U0 = U1;
+      if (mk & (mk - 1)) U1 = ld_blk(tl + tcB(idx - 1, s, nbs));
+    }
+  }
+}
+
+// writes the solved tail rows: y, and dx = y (dxmode 1) or dx += y (dxmode
+// 2, scenarios in mask; dx loaded by the caller ahead of the solve)
+template <typename T, int S>
+__device__ __forceinline__ void ltail_put(const Dims& D, St<T>& c, int s, int l, T y0, T y1, int dxmode, int mask,
+                                          double dx0, double dx1) {
+  if (l >= D.tail_t) return;
+  const int a = D.tail_base + l;
+  c.y[sP<S>(a, s)] = y0;
+  c.y[sP<S>(a, s) + 1] = y1;
+  if (dxmode == 1) {
+    c.dx[sP<S>(a, s)] = double(y0);
+    c.dx[sP<S>(a, s) + 1] = double(y1);
+  } else if (dxmode == 2 && ((mask >> s) & 1)) {
+    c.dx[sP<S>(a, s)] = dx0 + double(y0);
+    c.dx[sP<S>(a, s) + 1] = dx1 + double(y1);
   }
 }
 
 template <typename T, int S>
-__device__ __forceinline__ void ltail_bsolve(const Sym& m, const Dims& D, St<T>& c, const T* tl, const T* td,
+__device__ __forceinline__ void ltail_dx(const Dims& D, St<T>& c, int s, int l, int dxmode, double& dx0,
+                                         double& dx1) {
+  dx0 = dx1 = 0.0;
+  if (dxmode == 2 && l < D.tail_t) {
+    dx0 = c.dx[sP<S>(D.tail_base + l, s)];
+    dx1 = c.dx[sP<S>(D.tail_base + l, s) + 1];
+  }
+}
+
+// backward solve after the factorisation (its forward solve was fused in)
+template <typename T, int S>
+__device__ __forceinline__ void ltail_bsolve(const Dims& D, St<T>& c, const T* tl, const T* td, const int* tq,
                                              int tid, int nt, int dxmode = 0, int mask = 0) {
-  const int t = D.tail_t, tb = D.tail_base;
   const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
   for (int s = w; s < S; s += nw) {
     T y0 = T(0), y1 = T(0);
-    double dx0 = 0.0, dx1 = 0.0;
-    if (l < t) {
-      y0 = c.y[sP<S>(tb + l, s)];
-      y1 = c.y[sP<S>(tb + l, s) + 1];
-      if (dxmode == 2) { dx0 = c.dx[sP<S>(tb + l, s)]; dx1 = c.dx[sP<S>(tb + l, s) + 1]; }
+    double dx0, dx1;
+    ltail_dx<T, S>(D, c, s, l, dxmode, dx0, dx1);
+    if (l < D.tail_t) {
+      y0 = c.y[sP<S>(D.tail_base + l, s)];
+      y1 = c.y[sP<S>(D.tail_base + l, s) + 1];
     }
-    for (int j = t - 1; j >= 0; --j) {
-      if (l == j) {
-        const Blk<T> Di = ld_blk(td + sB<S>(j, s));
-        const T x0 = Di.a * y0 + Di.b * y1, x1 = Di.c * y0 + Di.d * y1;
-        y0 = x0;
-        y1 = x1;
-      }
-      const T xj0 = lane_bcast(y0, j), xj1 = lane_bcast(y1, j);
-      if (l < j) {
-        const int p = m.tail_cpos[l * t + j];
-        if (p >= 0) {
-          const Blk<T> U = ld_blk(tl + sB<S>(p, s));
-          y0 -= U.a * xj0 + U.b * xj1;
-          y1 -= U.c * xj0 + U.d * xj1;
-        }
-      }
-    }
-    if (l < t) {
-      c.y[sP<S>(tb + l, s)] = y0;
-      c.y[sP<S>(tb + l, s) + 1] = y1;
-      if (dxmode == 1) {
-        c.dx[sP<S>(tb + l, s)] = double(y0);
-        c.dx[sP<S>(tb + l, s) + 1] = double(y1);
-      } else if (dxmode == 2 && ((mask >> s) & 1)) {
-        c.dx[sP<S>(tb + l, s)] = dx0 + double(y0);
-        c.dx[sP<S>(tb + l, s) + 1] = dx1 + double(y1);
-      }
-    }
+    ltail_bs_one<T, S>(D, tl, td, tq, s, l, y0, y1);
+    ltail_put<T, S>(D, c, s, l, y0, y1, dxmode, mask, dx0, dx1);
+  }
+}
+
+// forward then backward solve of the tail rows (refinement), the forward
+// result kept in registers
+template <typename T, int S>
+__device__ __forceinline__ void ltail_fbsolve(const Sym& m, const Dims& D, St<T>& c, const T* tl, const T* td,
+                                              const int* tq, int tid, int nt, int dxmode, int mask) {
+  const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
+  for (int s = w; s < S; s += nw) {
+    T y0, y1;
+    double dx0, dx1;
+    ltail_dx<T, S>(D, c, s, l, dxmode, dx0, dx1);
+    ltail_fs_one<T, S>(m, D, c, tl, tq, s, l, y0, y1);
+    ltail_bs_one<T, S>(D, tl, td, tq, s, l, y0, y1);
+    ltail_put<T, S>(D, c, s, l, y0, y1, dxmode, mask, dx0, dx1);
   }
 }
 
@@ -1359,8 +1439,11 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
   const int wv = tid >> 6, ln = tid & 63;   // LDS-resident tails: wavefront wv <-> scenario wv
   unsigned char* stg = smem + kScratchBytes; // HBM-resident slices: staged level metadata
   T* tl = reinterpret_cast<T*>(smem + kScratchBytes + 4 * (size_t)kp.dims.chunk_ints);   // HBM: LDS tail
-  T* td = tl + (size_t)kp.dims.tail_nblk * S * 4;
+  T* td = tl + (size_t)kp.dims.tail_nbs * S * 4;
   T* ty = td + (size_t)kp.dims.tail_t * S * 4;
+  int* tq = reinterpret_cast<int*>(ty + (size_t)kp.dims.tail_t * S * 2);   // HBM: tail program prefix
+  if constexpr (!RES)
+    for (int q = tid; q < kp.dims.tail_prog_prefix; q += nt) tq[q] = m.tail_prog[q];
   TailRow<T> R;                             // this wavefront's factored tail rows
   pc.mark(PH_SETUP);
   while (true) {
@@ -1404,8 +1487,9 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       if (wv < S) rt_factor<T, S>(m, D, c, wv, ln, true, piv, R);
     } else {
       ltail_copy<T, S>(m, D, c, tl, tid, nt, false);
+      const int* tp = ltail_updates(m, D, stg, tid, nt);
       __syncthreads();
-      ltail_factor<T, S>(m, D, c, tl, td, ty, tid, nt, true, piv);
+      ltail_factor<T, S>(D, c, tl, td, ty, tq, tp, tid, nt, true, piv);
     }
     __syncthreads();
     pc.mark(PH_FACTOR_TAIL);
@@ -1418,7 +1502,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
     if constexpr (RES) {
       if (wv < S) rt_bsolve<T, S>(m, D, c, wv, ln, R, dx_set);
     } else {
-      ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt, dx_set);
+      ltail_bsolve<T, S>(D, c, tl, td, tq, tid, nt, dx_set);
     }
     __syncthreads();
     pc.mark(PH_BSOLVE_TAIL);
@@ -1455,9 +1539,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
             rt_bsolve<T, S>(m, D, c, wv, ln, R, dx_add, ref);
           }
         } else {
-          ltail_fsolve<T, S>(m, D, c, tl, tid, nt);
-          __syncthreads();
-          ltail_bsolve<T, S>(m, D, c, tl, td, tid, nt, dx_add, ref);
+          ltail_fbsolve<T, S>(m, D, c, tl, td, tq, tid, nt, dx_add, ref);
         }
         __syncthreads();
         pc.mark(PH_REFINE_TAIL);
@@ -1550,8 +1632,9 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       }
     } else {
       ltail_copy<T, S>(m, D, c, tl, tid, nt, false);
+      const int* tp = ltail_updates(m, D, stg, tid, nt);
       __syncthreads();
-      ltail_factor<T, S>(m, D, c, tl, td, ty, tid, nt, false, piv);
+      ltail_factor<T, S>(D, c, tl, td, ty, tq, tp, tid, nt, false, piv);
       __syncthreads();
       ltail_copy<T, S>(m, D, c, tl, tid, nt, true);
       ltail_store_dinv<T, S>(D, c, td, tid, nt);

@@ -449,25 +449,48 @@ int analyze(int32_t n_bus, const int32_t* bus_type, const int32_t* y_indptr,
   const int32_t tb = S.tail_base;
   {
     const int32_t t = S.tail_t;
+    // rows below each tail pivot with a block in its column, in row order
     std::vector<std::vector<int32_t>> by_piv(t);
     for (int32_t i = 0; i < t; ++i) {
       const int32_t a = tb + i;
-      for (int32_t p = S.rp[a]; p < S.diag[a]; ++p) {
-        const int32_t k = S.ci[p];
-        if (k < tb) continue;
-        by_piv[k - tb].push_back(a);
-        by_piv[k - tb].push_back(p - S.rp[a]);
-        by_piv[k - tb].push_back(S.upd_start[p]);
-        by_piv[k - tb].push_back(0);
+      for (int32_t p = S.rp[a]; p < S.diag[a]; ++p)
+        if (S.ci[p] >= tb) by_piv[S.ci[p] - tb].push_back(p);
+    }
+    if (S.tail_cblk.size() >= 2048 || t > 32) { err = "template: dense tail too large"; return PF_EINVAL; }
+    auto cidx = [&](int32_t a, int32_t p) { return S.tail_lbase[a - tb] + (p - S.rp[a]); };
+    S.tail_prog.assign(8 * (size_t)t, 0);
+    for (int32_t k = 0; k < t; ++k) {
+      const int32_t ak = tb + k;
+      const int32_t nu = S.rp[ak + 1] - S.diag[ak] - 1, ns = (int32_t)by_piv[k].size();
+      int32_t* r = &S.tail_prog[8 * k];
+      r[0] = cidx(ak, S.diag[ak]);
+      r[1] = cidx(ak, S.diag[ak] + 1);
+      r[2] = nu | (ns << 16);
+      uint32_t lm = 0, um = 0;
+      for (int32_t p = S.tail_split[k]; p < S.rp[ak + 1]; ++p) {
+        const int32_t j = S.ci[p] - tb;
+        if (p < S.diag[ak]) lm |= 1u << j;
+        else if (p > S.diag[ak]) um |= 1u << j;
+      }
+      r[5] = (int32_t)lm;
+      r[6] = (int32_t)um;
+    }
+    for (int32_t k = 0; k < t; ++k) {
+      S.tail_prog[8 * k + 3] = (int32_t)S.tail_prog.size();
+      for (int32_t p : by_piv[k]) S.tail_prog.push_back(cidx(S.prow[p], p) | ((S.prow[p] - tb) << 16));
+    }
+    S.tail_prog_prefix = (int32_t)S.tail_prog.size();
+    for (int32_t k = 0; k < t; ++k) {
+      const int32_t nu = S.tail_prog[8 * k + 2] & 0xffff;
+      S.tail_prog[8 * k + 4] = (int32_t)S.tail_prog.size();
+      for (int32_t p : by_piv[k]) {
+        const int32_t a = S.prow[p];
+        for (int32_t j = 0; j < nu; ++j) {
+          const int32_t tgt = S.tail_lbase[a - tb] + S.upd_tgt[S.upd_start[p] + j];
+          S.tail_prog.push_back(tgt | (cidx(a, p) << 11) | (j << 22));
+        }
       }
     }
-    S.tk_ptr.assign(t + 1, 0);
-    S.tstep4.clear();
-    for (int32_t k = 0; k < t; ++k) {
-      S.tk_ptr[k] = (int32_t)(S.tstep4.size() / 4);
-      S.tstep4.insert(S.tstep4.end(), by_piv[k].begin(), by_piv[k].end());
-    }
-    S.tk_ptr[t] = (int32_t)(S.tstep4.size() / 4);
   }
   // ---- factorisation tasks of the barrier-synchronised part: steps grouped
   // by (row, level of the pivot); pivots inside the tail and the tail's own

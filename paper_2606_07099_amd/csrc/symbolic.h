@@ -80,10 +80,21 @@ struct Symbolic {
   // compact index of position p of tail row l = tail_lbase[l] + (p - rp[tail_base + l]);
   // tail_cpos[i*t + j] = compact index of block (tail_base + i, tail_base + j) or -1
   std::vector<int32_t> tail_cblk, tail_lbase, tail_cpos;
-  // elimination steps of the tail pivots, pivot by pivot: tk_ptr[k] .. tk_ptr[k+1]
-  // index tstep4 records {row i, q = L position of (i, pivot) - rp[i], first
-  // target in upd_tgt, 0}
-  std::vector<int32_t> tk_ptr, tstep4;
+  // elimination program of the tail pivots in the compact numbering, read
+  // from LDS by the LDS copy of the tail.  Row/pivot k's record at 8k:
+  // {compact index of its pivot block, compact index of its first block right
+  // of the diagonal (the others follow), nu | ns << 16, offset of its step
+  // words, offset of its update words, mask of its blocks left of the
+  // diagonal (bit j: block (k, j) in the tail), mask of those right of it,
+  // 0}.  Step words (ns): compact index of L(i, k) | (i - tail_base) << 16
+  // for the rows i below with a block in column k.  Records and step words
+  // form the prefix [0, tail_prog_prefix); the update words follow: ns * nu
+  // per pivot, step by step, each target | L << 11 | j << 22 for target
+  // (i, column of the j-th block right of the pivot), all compact indices
+  // below 2048.  A row's blocks in tail columns have consecutive compact
+  // indices in column order, so the masks locate each of them.
+  std::vector<int32_t> tail_prog;
+  int32_t tail_prog_prefix = 0;
   std::vector<int32_t> lev_um_ptr, lev_um_rows;
   // Jacobian fill record of every block: Y_bus entry (-1: fill-in), bus of
   // the row, bus of the column, flags (1 diagonal, 2 row bus PV, 4 column bus PV)

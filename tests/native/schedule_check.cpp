@@ -42,9 +42,13 @@
 // Input (text): n_bus n_branch, then n_bus bus types, then n_branch lines
 // "from to r x b".  Output: one summary line; exit status 0 when every check
 // holds, 1 with the first violations printed otherwise.
+#include <algorithm>
+#include <array>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <random>
 #include <set>
 #include <string>
 #include <vector>
@@ -354,21 +358,180 @@ int main(int argc, char** argv) {
   for (int a = tb; a < nb; ++a)
     for (int p = S.rp[a]; p < S.tail_split[a - tb]; ++p) CHECK(w_pos[p] < e_end, "tail row %d", a);
 
-  // ---- dense tail: per-pivot step lists and masks
+  // ---- dense tail: the elimination program of the LDS tail copy and masks
   const int tt = S.tail_t;
   {
+    const int nblk = (int)S.tail_cblk.size();
+    auto cidx = [&](int a, int p) { return S.tail_lbase[a - tb] + (p - S.rp[a]); };
+    auto rec = [&](int k, int f) { return S.tail_prog[8 * k + f]; };
     std::vector<int> cover(nnzb, 0);
-    for (int k = 0; k < tt; ++k)
-      for (int st = S.tk_ptr[k]; st < S.tk_ptr[k + 1]; ++st) {
-        const int i = S.tstep4[4 * st], q = S.tstep4[4 * st + 1];
-        const int p = S.rp[i] + q;
-        CHECK(i > tb + k - 1 && i < nb && S.ci[p] == tb + k, "tail step list of pivot %d", k);
-        CHECK(S.tstep4[4 * st + 2] == S.upd_start[p], "tail step targets of pivot %d", k);
-        cover[p]++;
+    CHECK(S.tail_prog.size() >= 8 * (size_t)tt && S.tail_prog_prefix >= 8 * tt &&
+          (size_t)S.tail_prog_prefix <= S.tail_prog.size(), "tail program extent");
+    for (int k = 0; k < tt && !S.tail_prog.empty(); ++k) {
+      const int ak = tb + k;
+      const int dk = rec(k, 0), ks = rec(k, 1), nu = rec(k, 2) & 0xffff, ns = rec(k, 2) >> 16;
+      const int soff = rec(k, 3), uoff = rec(k, 4);
+      const unsigned lm = (unsigned)rec(k, 5), um = (unsigned)rec(k, 6);
+      CHECK(dk == cidx(ak, S.diag[ak]) && S.tail_cblk[dk] == S.diag[ak], "tail program pivot %d", k);
+      CHECK(nu == S.rp[ak + 1] - S.diag[ak] - 1, "tail program pivot %d: U count", k);
+      CHECK(nu == 0 || ks == dk + 1, "tail program pivot %d: first U", k);
+      CHECK(soff + ns <= S.tail_prog_prefix, "tail program pivot %d: steps outside the prefix", k);
+      CHECK(uoff >= S.tail_prog_prefix && uoff + (size_t)ns * nu <= S.tail_prog.size(),
+            "tail program pivot %d: updates extent", k);
+      // masks: the row's blocks in tail columns have consecutive compact
+      // indices in column order, L part, pivot, U part
+      int rank = 0;
+      for (int j = 0; j < tt; ++j) {
+        const int cp = S.tail_cpos[(size_t)k * tt + j];
+        const bool inl = (lm >> j) & 1u, inu = (um >> j) & 1u;
+        CHECK(inl == (cp >= 0 && j < k) && inu == (cp >= 0 && j > k), "tail masks row %d col %d", k, j);
+        if (cp >= 0) {
+          CHECK(cp == dk - __builtin_popcount(lm) + rank, "tail row %d: compact order at col %d", k, j);
+          ++rank;
+        }
       }
+      CHECK(__builtin_popcount(um) == nu, "tail row %d: U mask count", k);
+      std::set<int> targets, lus;
+      for (int j = 0; j < nu; ++j) lus.insert(ks + j);
+      lus.insert(dk);
+      for (int si = 0; si < ns; ++si) {
+        const int w = S.tail_prog[soff + si], lc = w & 0xffff, ir = w >> 16;
+        const int a = tb + ir;
+        CHECK(ir > k && ir < tt, "tail program pivot %d: step row %d", k, ir);
+        if (!(ir > k && ir < tt)) continue;
+        const int p = S.tail_cblk[lc];
+        CHECK(lc >= 0 && lc < nblk && S.prow[p] == a && S.ci[p] == ak && p < S.diag[a],
+              "tail program pivot %d: L block of row %d", k, ir);
+        cover[p]++;
+        lus.insert(lc);
+        for (int j = 0; j < nu; ++j) {
+          const unsigned r = (unsigned)S.tail_prog[uoff + (size_t)si * nu + j];
+          const int tg = (int)(r & 2047u), l2 = (int)((r >> 11) & 2047u), jj = (int)(r >> 22);
+          const int col = S.ci[S.diag[ak] + 1 + j];
+          int want = -1;
+          for (int q = S.rp[a]; q < S.rp[a + 1]; ++q)
+            if (S.ci[q] == col) want = cidx(a, q);
+          CHECK(l2 == lc && jj == j && tg == want && want >= 0, "tail program pivot %d: update (%d, %d)", k, ir, j);
+          CHECK(targets.insert(tg).second, "tail program pivot %d: target twice", k);
+        }
+      }
+      for (int tg : targets) CHECK(!lus.count(tg), "tail program pivot %d: target is an operand", k);
+    }
     for (int a = tb; a < nb; ++a)
       for (int p = S.rp[a]; p < S.diag[a]; ++p)
         if (S.ci[p] >= tb) CHECK(cover[p] == 1, "tail L(%d,%d) covered %d times", a, S.ci[p], cover[p]);
+    // numeric replay: the program's factorisation and the mask-walking
+    // triangular solves on random values of the tail pattern, against a
+    // dense right-looking block LU and dense solves of the same t x t block
+    // matrix
+    if (tt > 0 && !S.tail_prog.empty()) {
+      using B4 = std::array<double, 4>;
+      std::mt19937_64 rng(7);
+      std::uniform_real_distribution<double> U(-1.0, 1.0);
+      std::vector<B4> v(nblk), A((size_t)tt * tt, {0, 0, 0, 0}), dinv(tt);
+      for (int i = 0; i < tt; ++i)
+        for (int j = 0; j < tt; ++j) {
+          const int cp = S.tail_cpos[(size_t)i * tt + j];
+          if (cp < 0) continue;
+          B4 b = {U(rng), U(rng), U(rng), U(rng)};
+          if (i == j) { b[0] += 4.0 * tt; b[3] += 4.0 * tt; }
+          v[cp] = b;
+          A[(size_t)i * tt + j] = b;
+        }
+      auto mul = [](const B4& x, const B4& y) {
+        return B4{x[0] * y[0] + x[1] * y[2], x[0] * y[1] + x[1] * y[3], x[2] * y[0] + x[3] * y[2],
+                  x[2] * y[1] + x[3] * y[3]};
+      };
+      auto inv = [](const B4& x) {
+        const double d = x[0] * x[3] - x[1] * x[2];
+        return B4{x[3] / d, -x[1] / d, -x[2] / d, x[0] / d};
+      };
+      for (int k = 0; k < tt; ++k) {
+        const int dk = rec(k, 0), ks = rec(k, 1), nu = rec(k, 2) & 0xffff, ns = rec(k, 2) >> 16;
+        const B4 Di = inv(v[dk]);
+        dinv[k] = Di;
+        for (size_t q = 0; q < (size_t)ns * nu; ++q) {
+          const unsigned r = (unsigned)S.tail_prog[rec(k, 4) + q];
+          const B4 M = mul(mul(v[(r >> 11) & 2047u], Di), v[ks + (r >> 22)]);
+          for (int e = 0; e < 4; ++e) v[r & 2047u][e] -= M[e];
+        }
+        for (int si = 0; si < ns; ++si) {
+          const int lc = S.tail_prog[rec(k, 3) + si] & 0xffff;
+          v[lc] = mul(v[lc], Di);
+        }
+        const B4 Dd = inv(A[(size_t)k * tt + k]);
+        for (int i = k + 1; i < tt; ++i) {
+          const B4 L = mul(A[(size_t)i * tt + k], Dd);
+          for (int j = k + 1; j < tt; ++j) {
+            const B4 M = mul(L, A[(size_t)k * tt + j]);
+            for (int e = 0; e < 4; ++e) A[(size_t)i * tt + j][e] -= M[e];
+          }
+          A[(size_t)i * tt + k] = L;
+        }
+      }
+      double worst = 0.0;
+      for (int i = 0; i < tt; ++i)
+        for (int j = 0; j < tt; ++j) {
+          const int cp = S.tail_cpos[(size_t)i * tt + j];
+          for (int e = 0; e < 4; ++e) {
+            const double ref = A[(size_t)i * tt + j][e];
+            const double got = cp < 0 ? 0.0 : v[cp][e];
+            worst = std::max(worst, std::fabs(got - ref) / (1.0 + std::fabs(ref)));
+          }
+        }
+      CHECK(worst < 1e-12, "tail program replay differs from a dense LU by %g", worst);
+      // solves: row i walks its blocks by its masks (forward: lowest column
+      // first, backward: highest first), as the lanes do
+      std::vector<double> y(2 * tt), ref(2 * tt);
+      for (auto& x : y) x = U(rng);
+      ref = y;
+      for (int k = 0; k < tt; ++k)
+        for (int i = k + 1; i < tt; ++i) {
+          const B4& L = A[(size_t)i * tt + k];
+          ref[2 * i] -= L[0] * ref[2 * k] + L[1] * ref[2 * k + 1];
+          ref[2 * i + 1] -= L[2] * ref[2 * k] + L[3] * ref[2 * k + 1];
+        }
+      for (int j = tt - 1; j >= 0; --j) {
+        const B4 D = inv(A[(size_t)j * tt + j]);
+        const double x0 = D[0] * ref[2 * j] + D[1] * ref[2 * j + 1], x1 = D[2] * ref[2 * j] + D[3] * ref[2 * j + 1];
+        ref[2 * j] = x0;
+        ref[2 * j + 1] = x1;
+        for (int i = 0; i < j; ++i) {
+          const B4& Ub = A[(size_t)i * tt + j];
+          ref[2 * i] -= Ub[0] * x0 + Ub[1] * x1;
+          ref[2 * i + 1] -= Ub[2] * x0 + Ub[3] * x1;
+        }
+      }
+      for (int k = 0; k < tt; ++k) {   // forward, in pivot order
+        for (int i = k + 1; i < tt; ++i) {
+          const unsigned lm = (unsigned)rec(i, 5);
+          if (!((lm >> k) & 1u)) continue;
+          const int idx = rec(i, 0) - __builtin_popcount(lm) + __builtin_popcount(lm & ((1u << k) - 1u));
+          const B4& L = v[idx];
+          y[2 * i] -= L[0] * y[2 * k] + L[1] * y[2 * k + 1];
+          y[2 * i + 1] -= L[2] * y[2 * k] + L[3] * y[2 * k + 1];
+        }
+      }
+      for (int j = tt - 1; j >= 0; --j) {
+        const B4& D = dinv[j];
+        const double x0 = D[0] * y[2 * j] + D[1] * y[2 * j + 1], x1 = D[2] * y[2 * j] + D[3] * y[2 * j + 1];
+        y[2 * j] = x0;
+        y[2 * j + 1] = x1;
+        for (int i = 0; i < j; ++i) {
+          const unsigned um = (unsigned)rec(i, 6);
+          if (!((um >> j) & 1u)) continue;
+          const int idx = rec(i, 0) + __builtin_popcount(um & ((j < 31 ? (2u << j) : 0u) - 1u));
+          const B4& Ub = v[idx];
+          y[2 * i] -= Ub[0] * x0 + Ub[1] * x1;
+          y[2 * i + 1] -= Ub[2] * x0 + Ub[3] * x1;
+        }
+      }
+      double werr = 0.0;
+      for (int i = 0; i < 2 * tt; ++i) werr = std::max(werr, std::fabs(y[i] - ref[i]) / (1.0 + std::fabs(ref[i])));
+      CHECK(werr < 1e-12, "tail solves differ from dense solves by %g", werr);
+      printf("tail_replay_err %.3g solve_err %.3g over %d pivots, %d blocks, program %zu words (prefix %d)\n",
+             worst, werr, tt, nblk, S.tail_prog.size(), S.tail_prog_prefix);
+    }
     if (tt > 0 && tt <= 32)
       for (int i = 0; i < tt; ++i)
         for (int j = 0; j < tt; ++j) {
