@@ -98,14 +98,17 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 // slices of several scenarios, whose bus-order passes still read whole runs;
 // a slice of one scenario keeps one array per value, so that its bus-order
 // passes read consecutive buses of one array.
-sable::StateLayout make_layout(int n_bus, int nb, int nnzb, bool grouped) {
+// gk: how the eight gathered values e f |V| 1/|V| I_re I_im dV_re dV_im of a
+// bus are grouped: 8 all together, 2 in the pairs (e, f), (|V|, 1/|V|),
+// (I_re, I_im), (dV_re, dV_im) that the passes read together, 1 one array each
+sable::StateLayout make_layout(int n_bus, int nb, int nnzb, int gk) {
   sable::StateLayout L{};
   const int nbr = round_up(n_bus, 4), v2 = round_up(2 * nb, 4);
   int o = 0;
-  L.gk = grouped ? 8 : 1;
-  const int fs = grouped ? 1 : nbr;   // offset between consecutive values of a bus
-  L.o_e = o; L.o_f = o + fs; L.o_vm = o + 2 * fs; L.o_rvm = o + 3 * fs;
-  L.o_ire = o + 4 * fs; L.o_iim = o + 5 * fs; L.o_dvr = o + 6 * fs; L.o_dvi = o + 7 * fs;
+  L.gk = gk;
+  int* fld[8] = {&L.o_e, &L.o_f, &L.o_vm, &L.o_rvm, &L.o_ire, &L.o_iim, &L.o_dvr, &L.o_dvi};
+  for (int k = 0; k < 8; ++k)
+    *fld[k] = o + (gk == 8 ? k : gk == 2 ? (k >> 1) * 2 * nbr + (k & 1) : k * nbr);
   o += 8 * nbr;
   L.o_va = o; o += nbr; L.o_ps = o; o += nbr; L.o_qs = o; o += nbr; L.o_aux = o; o += nbr;
   L.o_F = o; o += v2; L.o_dx = o; o += v2;
@@ -497,7 +500,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   // one wavefront per scenario's register-resident tail) when they fit,
   // choosing S to maximise the scenarios resident per CU; HBM-resident
   // slices of up to 16 scenarios otherwise
-  t->lay = make_layout(S.n_bus, S.nb, S.nnzb(), false);
+  t->lay = make_layout(S.n_bus, S.nb, S.nnzb(), 1);
   t->llay = make_lds_layout(S.n_bus, S.nb, S.nnzb(), t->fp32);
   const size_t lds_cu = std::max<size_t>(max_lds, (size_t)prop.maxSharedMemoryPerMultiProcessor);
   const size_t per_scen = 8 * (size_t)t->llay.sd + tsz * (size_t)t->llay.st;
@@ -540,7 +543,9 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     t->lds_res = false;
     const int sl = hbm_slice;
     t->slice = sl;
-    t->lay = make_layout(S.n_bus, S.nb, S.nnzb(), sl > 1);
+    // grouped per-bus values: a slice of several scenarios reads a bus's
+    // values of all of them at once, a slice of one reads them in pairs
+    t->lay = make_layout(S.n_bus, S.nb, S.nnzb(), sl > 1 ? 8 : 2);
     t->lds_bytes = sable::kScratchBytes + 4 * (size_t)dm.chunk_ints + tail_bytes(sl);
     // the adjoint reads this slice workspace in place
     t->adj_slice = -sl;

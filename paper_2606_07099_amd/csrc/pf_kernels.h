@@ -95,12 +95,13 @@ struct Dims {
 // e f vm va ire iim ps qs dvr dvi aux rvm (= 1/|V|) [n_bus], F dx [2 nb].  Factor-
 // precision arrays (T): y [2 nb], lu [4 nnzb], dinv [4 nb].  In a slice of S
 // scenarios every array is interleaved by scenario (element k of scenario s
-// at k*S + s) and starts at offset*S, except that with gk = 8 the eight
-// gathered per-bus values e f vm rvm ire iim dvr dvi are grouped by bus:
-// their offsets are consecutive and bus i of scenario s sits at i*gk*S + s.
+// at k*S + s) and starts at offset*S, except that with gk = 8 (gk = 2) the
+// eight gathered per-bus values e f vm rvm ire iim dvr dvi are grouped by bus
+// (in the pairs e f, vm rvm, ire iim, dvr dvi): the grouped offsets are
+// consecutive and bus i of scenario s sits at i*gk*S + s past them.
 struct StateLayout {
   int o_e, o_f, o_vm, o_va, o_ire, o_iim, o_ps, o_qs, o_dvr, o_dvi, o_aux, o_rvm, o_F, o_dx;
-  int gk;  // 8: grouped per-bus values (HBM workspace), 1: one array each
+  int gk;  // 8: the eight per-bus values grouped, 2: in pairs, 1: one array each
   int sd;  // doubles per scenario
   int o_y, o_lu, o_dinv;
   int st;  // T elements per scenario
