@@ -449,7 +449,12 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     delete t;
     return fail(PF_EINVAL, "pf_template_build: the dense tail does not fit in LDS");
   }
-  const size_t room = (max_lds - sable::kScratchBytes - tail_bytes(hbm_slice)) / 4;
+  // the slice's right-hand side / solution vector y of the triangular
+  // solves lives in LDS too when that leaves the full metadata budget
+  const size_t y_bytes = ((size_t)2 * S.nb * hbm_slice * tsz + 15) / 16 * 16;
+  size_t room = (max_lds - sable::kScratchBytes - tail_bytes(hbm_slice)) / 4;
+  const bool y_in_lds = room >= y_bytes / 4 + kChunkInts;
+  if (y_in_lds) room -= y_bytes / 4;
   const int32_t budget = (int32_t)std::min<size_t>(kChunkInts, room / 4 * 4);
   rc = sable::build_level_chunks(S, budget, chunks, err);
   if (rc != 0) { delete t; return fail(PF_EINVAL, err); }
@@ -547,6 +552,12 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     // values of all of them at once, a slice of one reads them in pairs
     t->lay = make_layout(S.n_bus, S.nb, S.nnzb(), sl > 1 ? 8 : 2);
     t->lds_bytes = sable::kScratchBytes + 4 * (size_t)dm.chunk_ints + tail_bytes(sl);
+    t->lds_bytes = (t->lds_bytes + 15) / 16 * 16;
+    dm.y_lds_off = 0;
+    if (y_in_lds) {
+      dm.y_lds_off = (int)t->lds_bytes;
+      t->lds_bytes += y_bytes;
+    }
     // the adjoint reads this slice workspace in place
     t->adj_slice = -sl;
     t->adj_nt = std::min(512, std::max(256, 64 * sl));

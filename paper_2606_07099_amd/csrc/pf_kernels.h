@@ -89,6 +89,7 @@ struct Dims {
   int tail_prog_ints;             // words of the tail program
   int tail_prog_prefix;           // its records, step and column words: kept in LDS
   int tail_prog_lds;              // 1: its update words staged in the metadata area, 0: read in place
+  int y_lds_off;                  // HBM-resident slices: byte offset of y in LDS (0: y stays in HBM)
 };
 
 // Offsets of the per-scenario arrays, in elements.  FP64 arrays:

@@ -1442,8 +1442,12 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
   T* td = tl + (size_t)kp.dims.tail_nbs * S * 4;
   T* ty = td + (size_t)kp.dims.tail_t * S * 4;
   int* tq = reinterpret_cast<int*>(ty + (size_t)kp.dims.tail_t * S * 2);   // HBM: tail program prefix
-  if constexpr (!RES)
+  if constexpr (!RES) {
     for (int q = tid; q < kp.dims.tail_prog_prefix; q += nt) tq[q] = m.tail_prog[q];
+    // the right-hand side / solution of the triangular solves, when the
+    // slice's copy fits in LDS: every solve's gathers then stay on chip
+    if (kp.dims.y_lds_off) c.y = reinterpret_cast<T*>(smem + kp.dims.y_lds_off);
+  }
   TailRow<T> R;                             // this wavefront's factored tail rows
   pc.mark(PH_SETUP);
   while (true) {
