@@ -111,7 +111,7 @@ sable::StateLayout make_layout(int n_bus, int nb, int nnzb, int gk) {
     *fld[k] = o + (gk == 8 ? k : gk == 2 ? (k >> 1) * 2 * nbr + (k & 1) : k * nbr);
   o += 8 * nbr;
   L.o_va = o; o += nbr; L.o_ps = o; o += nbr; L.o_qs = o; o += nbr; L.o_aux = o; o += nbr;
-  L.o_F = o; o += v2; L.o_dx = o; o += v2;
+  L.o_F = o; o += 2 * nbr; L.o_dx = o; o += v2;   // F by bus, dx by block row
   L.sd = o;
   int t = 0;
   L.o_y = t; t += round_up(2 * nb, 8);
@@ -130,7 +130,7 @@ sable::StateLayout make_lds_layout(int n_bus, int nb, int nnzb, bool mixed) {
   L.o_e = o; o += n_bus; L.o_f = o; o += n_bus; L.o_vm = o; o += n_bus; L.o_va = o; o += n_bus;
   L.o_ire = o; o += n_bus; L.o_iim = o; o += n_bus; L.o_ps = o; o += n_bus; L.o_qs = o; o += n_bus;
   L.o_rvm = o; o += n_bus;
-  L.o_F = o; o += 2 * nb; L.o_dx = o; o += 2 * nb;
+  L.o_F = o; o += 2 * n_bus; L.o_dx = o; o += 2 * nb;
   if (mixed) {
     L.o_dvr = o; o += n_bus; L.o_dvi = o; o += n_bus;
   } else {
@@ -155,7 +155,7 @@ sable::StateLayout make_adj_layout(int n_bus, int nb, int nnzb) {
   L.o_e = o; o += n_bus; L.o_f = o; o += n_bus; L.o_vm = o; o += n_bus;
   L.o_ire = o; o += n_bus; L.o_iim = o; o += n_bus;
   L.o_dvr = o; o += n_bus; L.o_dvi = o; o += n_bus; L.o_aux = o; o += n_bus;
-  L.o_F = o; o += 2 * nb; L.o_dx = o; o += 2 * nb;
+  L.o_F = o; o += 2 * n_bus; L.o_dx = o; o += 2 * nb;
   L.o_va = L.o_ps = L.o_qs = L.o_rvm = 0;
   L.sd = round_up(o, 2);
   int t = 0;

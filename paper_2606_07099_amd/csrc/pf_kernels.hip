@@ -375,9 +375,10 @@ __device__ __forceinline__ void yrow_multi(const Sym& m, const double* xr, const
 // items per thread and row entries per round of the bus-indexed passes
 constexpr int kBusU = 1, kBusW = 4;
 
-// I = Y V, S = V conj(I), F1 = spec - calc on the block rows; ||F1||_inf per
-// scenario.  With RHS the Newton step's right-hand side y = -F1 is written too.
-template <typename T, int S, bool RHS>
+// I = Y V, S = V conj(I), F1 = spec - calc of every bus (F indexed by bus,
+// two entries each: dP, and dQ on PQ buses); ||F1||_inf per scenario.  The
+// Newton step's right-hand side y = -F1 goes to the block rows as well.
+template <typename T, int S>
 __device__ __forceinline__ void phase_mismatch(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
                                unsigned char* scr) {
   double mx = 0.0;
@@ -414,12 +415,10 @@ __device__ __forceinline__ void phase_mismatch(const Sym& m, const Dims& D, St<T
         const double Q = fi[u] * ir[u] - ei[u] * ii[u];
         const double F0 = ps[u] - P;
         const double F1 = bt[u] == 0 ? qs[u] - Q : 0.0;
-        c.F[sP<S>(a[u], s)] = F0;
-        c.F[sP<S>(a[u], s) + 1] = F1;
-        if (RHS) {
-          c.y[sP<S>(a[u], s)] = T(-F0);
-          c.y[sP<S>(a[u], s) + 1] = T(-F1);
-        }
+        c.F[sP<S>(i[u], s)] = F0;
+        c.F[sP<S>(i[u], s) + 1] = F1;
+        c.y[sP<S>(a[u], s)] = T(-F0);
+        c.y[sP<S>(a[u], s) + 1] = T(-F1);
         bad |= !(isfinite(F0) && isfinite(F1));
         mx = fmax(mx, fmax(fabs(F0), fabs(F1)));
       }
@@ -1309,8 +1308,8 @@ __device__ __forceinline__ void phase_residual(const Sym& m, const Dims& D, St<T
       dvr[u] = c.dvr[go];
       dvi[u] = c.dvi[go];
       const int pa = a[u] >= 0 ? a[u] : 0;
-      F0[u] = c.F[sP<S>(pa, s)];
-      F1[u] = c.F[sP<S>(pa, s) + 1];
+      F0[u] = c.F[sP<S>(i[u], s)];
+      F1[u] = c.F[sP<S>(i[u], s) + 1];
     }
     double dir[kBusU], dii[kBusU];
     yrow_multi<S, kBusU, kBusW>(m, c.dvr, c.dvi, c.gs, i, s, v, dir, dii);
@@ -1449,9 +1448,13 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
     if (kp.dims.y_lds_off) c.y = reinterpret_cast<T*>(smem + kp.dims.y_lds_off);
   }
   TailRow<T> R;                             // this wavefront's factored tail rows
+  // slices of several scenarios hand the backward solves' results to dx as
+  // they write them
+  constexpr bool fuse = S > 1 && !RES;
+  constexpr int dx_set = fuse ? 1 : 0, dx_add = fuse ? 2 : 0;
   pc.mark(PH_SETUP);
   while (true) {
-    phase_mismatch<T, S, (S > 1 && !RES)>(m, D, c, tid, nt, scr);
+    phase_mismatch<T, S>(m, D, c, tid, nt, scr);
     pc.mark(PH_MISMATCH);
     for (int s = 0; s < S; ++s) {
       if (!((act >> s) & 1)) continue;
@@ -1472,16 +1475,10 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       break;
     }
     if (!act) break;
-    // slices of several scenarios form y = -F1 in the mismatch pass and hand
-    // the backward solves' results to dx as they write them; a slice of one
-    // scenario scatters each of those stores to its own line, on the critical
-    // path of a level, so it runs them as separate streaming passes instead
-    constexpr bool fuse = S > 1 && !RES;
-    constexpr int dx_set = fuse ? 1 : 0, dx_add = fuse ? 2 : 0;
-    if (!fuse) {
-      for (int q = tid; q < 2 * nb * S; q += nt) c.y[q] = T(-c.F[q]);
-      __syncthreads();
-    }
+    // slices of several scenarios hand the backward solves' results to dx
+    // as they write them; a slice of one scenario scatters each of those
+    // stores to its own line, on the critical path of a level, so it updates
+    // dx in a streaming pass of its own
     phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
     pc.mark(PH_FILL);
     pc.count(PH_NEWTON_STEPS);
@@ -1615,8 +1612,8 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       if (b >= kp.count || a < 0) continue;
       double* o = kp.out + (size_t)b * nj;
       if (kp.mode == MODE_EVAL_MISMATCH) {
-        o[m.ord_p[i]] = c.F[sP<S>(a, s)];
-        if (m.bus_type[i] == 0) o[D.npvpq + m.ord_q[i]] = c.F[sP<S>(a, s) + 1];
+        o[m.ord_p[i]] = c.F[sP<S>(i, s)];
+        if (m.bus_type[i] == 0) o[D.npvpq + m.ord_q[i]] = c.F[sP<S>(i, s) + 1];
       } else {
         o[D.npq + m.ord_p[i]] = c.dx[sP<S>(a, s)];
         if (m.bus_type[i] == 0) o[m.ord_q[i]] = c.dx[sP<S>(a, s) + 1];
