@@ -52,15 +52,15 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # the kernel sources they were taken on; a changed kernel reports null.
 # Sources: profiles/*_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "d827ae71c357a811878c0f81165bdf583634bd5a0e3bc74519e0dcb990ef2580": {
-        "c1/mixed": 7017145,
-        "c1/fp64": 7977664,
-        "c2/mixed": 46947579022,
-        "c2/fp64": 49097088470,
-        "c3/mixed": 3747991460,
-        "c3/fp64": 4075729938,
-        "c4/mixed": 67151399410,
-        "c4/fp64": 56105196813,
+    "be7f9b428bf395e7a6cfdbda31b1c4faa29e3d558c1472a0d4127f1903c9a038": {
+        "c1/mixed": 7013049,
+        "c1/fp64": 6929088,
+        "c2/mixed": 46068310827,
+        "c2/fp64": 48908897607,
+        "c3/mixed": 3403600997,
+        "c3/fp64": 3611531585,
+        "c4/mixed": 49566288999,
+        "c4/fp64": 50702192941,
     },
 }
 
