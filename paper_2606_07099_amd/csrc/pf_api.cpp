@@ -139,7 +139,7 @@ sable::StateLayout make_lds_layout(int n_bus, int nb, int nnzb, bool mixed) {
   L.o_aux = 0;
   L.sd = round_up(o, 2);
   int t = 0;
-  L.o_y = t; t += 2 * nb;
+  L.o_y = t; t += round_up(2 * nb, 4);   // blocks start 16-byte aligned
   L.o_lu = t; t += 4 * nnzb;
   L.o_dinv = t; t += 4 * nb;
   L.st = round_up(t, 4);
@@ -159,7 +159,7 @@ sable::StateLayout make_adj_layout(int n_bus, int nb, int nnzb) {
   L.o_va = L.o_ps = L.o_qs = L.o_rvm = 0;
   L.sd = round_up(o, 2);
   int t = 0;
-  L.o_y = t; t += 2 * nb;
+  L.o_y = t; t += round_up(2 * nb, 4);   // blocks start 16-byte aligned
   L.o_lu = t; t += 4 * nnzb;
   L.o_dinv = t; t += 4 * nb;
   L.st = round_up(t, 4);

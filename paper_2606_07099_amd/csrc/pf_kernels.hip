@@ -63,16 +63,41 @@ struct PhaseClock {
 template <typename T>
 struct Blk { T a, b, c, d; };  // row-major 2x2 block [[a, b], [c, d]]
 
-template <typename T>
-__device__ __forceinline__ Blk<T> ld_blk(const T* p) { return {p[0], p[1], p[2], p[3]}; }
-template <typename T>
-__device__ __forceinline__ void st_blk(T* p, const Blk<T>& x) { p[0] = x.a; p[1] = x.b; p[2] = x.c; p[3] = x.d; }
+// every block (factors, pivot inverses, the LDS tail copy) starts 16-byte
+// aligned in every layout, so a block moves in 16-byte vector operations
+__device__ __forceinline__ Blk<float> ld_blk(const float* p) {
+  using V = float __attribute__((ext_vector_type(4)));
+  const V v = *reinterpret_cast<const V*>(__builtin_assume_aligned(p, 16));
+  return {v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ Blk<double> ld_blk(const double* p) {
+  using V = double __attribute__((ext_vector_type(2)));
+  const V* q = reinterpret_cast<const V*>(__builtin_assume_aligned(p, 16));
+  const V u = q[0], v = q[1];
+  return {u.x, u.y, v.x, v.y};
+}
+__device__ __forceinline__ void st_blk(float* p, const Blk<float>& x) {
+  using V = float __attribute__((ext_vector_type(4)));
+  *reinterpret_cast<V*>(__builtin_assume_aligned(p, 16)) = V{x.a, x.b, x.c, x.d};
+}
+__device__ __forceinline__ void st_blk(double* p, const Blk<double>& x) {
+  using V = double __attribute__((ext_vector_type(2)));
+  V* q = reinterpret_cast<V*>(__builtin_assume_aligned(p, 16));
+  q[0] = V{x.a, x.b};
+  q[1] = V{x.c, x.d};
+}
 // streaming block load: HBM values read once per pass, marked non-temporal
 // so that they do not displace the gathered unknowns from the caches
-template <typename T>
-__device__ __forceinline__ Blk<T> ld_blk_nt(const T* p) {
-  return {__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1), __builtin_nontemporal_load(p + 2),
-          __builtin_nontemporal_load(p + 3)};
+__device__ __forceinline__ Blk<float> ld_blk_nt(const float* p) {
+  using V = float __attribute__((ext_vector_type(4)));
+  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(__builtin_assume_aligned(p, 16)));
+  return {v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ Blk<double> ld_blk_nt(const double* p) {
+  using V = double __attribute__((ext_vector_type(2)));
+  const V* q = reinterpret_cast<const V*>(__builtin_assume_aligned(p, 16));
+  const V u = __builtin_nontemporal_load(q), v = __builtin_nontemporal_load(q + 1);
+  return {u.x, u.y, v.x, v.y};
 }
 
 template <typename T>
