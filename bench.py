@@ -52,15 +52,15 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # the kernel sources they were taken on; a changed kernel reports null.
 # Sources: profiles/*_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "be7f9b428bf395e7a6cfdbda31b1c4faa29e3d558c1472a0d4127f1903c9a038": {
-        "c1/mixed": 7013049,
-        "c1/fp64": 6929088,
-        "c2/mixed": 46068310827,
-        "c2/fp64": 48908897607,
-        "c3/mixed": 3403600997,
-        "c3/fp64": 3611531585,
-        "c4/mixed": 49566288999,
-        "c4/fp64": 50702192941,
+    "273fdad700f8a95fce1ffcf8834e0c844ff427540d3a4e70e1cf1fd64cb7951f": {
+        "c1/mixed": 7024313,
+        "c1/fp64": 6926016,
+        "c2/mixed": 46056349581,
+        "c2/fp64": 48900603732,
+        "c3/mixed": 3401512094,
+        "c3/fp64": 3613741311,
+        "c4/mixed": 49551544488,
+        "c4/fp64": 50563092537,
     },
 }
 
