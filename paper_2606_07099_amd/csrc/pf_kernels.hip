@@ -232,12 +232,18 @@ __device__ __forceinline__ void fill_gather(const Sym& m, const St<T>& c, int s,
   q.g = r.x < 0 ? 0.0 : m.y_g[r.x];
   q.b = r.x < 0 ? 0.0 : m.y_b[r.x];
   const int is = c.g(r.y, s), ms = c.g(r.z, s);
-  q.x[0] = c.e[is];
-  q.x[1] = c.f[is];
+  // one-scenario slices skip the gathers of fill-in positions (no value);
+  // in wider slices the masked loads cost more than the lines they save
+  const bool fill_in = S == 1 && r.x < 0 && !dg;
+  q.x[0] = fill_in ? 0.0 : c.e[is];
+  q.x[1] = fill_in ? 0.0 : c.f[is];
   if (dg) {
     q.x[2] = c.vm[is]; q.x[3] = c.rvm[is]; q.x[4] = c.ire[is]; q.x[5] = c.iim[is];
   } else {
-    q.x[2] = c.e[ms]; q.x[3] = c.f[ms]; q.x[4] = c.rvm[ms]; q.x[5] = 0.0;
+    q.x[2] = fill_in ? 0.0 : c.e[ms];
+    q.x[3] = fill_in ? 0.0 : c.f[ms];
+    q.x[4] = fill_in ? 0.0 : c.rvm[ms];
+    q.x[5] = 0.0;
   }
 }
 
