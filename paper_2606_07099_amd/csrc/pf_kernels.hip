@@ -242,16 +242,29 @@ __device__ __forceinline__ void fill_gather(const Sym& m, const St<T>& c, int s,
   } else {
     q.x[2] = fill_in ? 0.0 : c.e[ms];
     q.x[3] = fill_in ? 0.0 : c.f[ms];
-    q.x[4] = fill_in ? 0.0 : c.rvm[ms];
+    // one-scenario slices form the column bus's 1/|V| from its e and f
+    // (hardware estimate and two Newton steps) instead of gathering a third
+    // line per block; wider slices read it with the others
+    q.x[4] = S == 1 ? 0.0 : c.rvm[ms];
     q.x[5] = 0.0;
   }
 }
 
-template <typename T>
-__device__ __forceinline__ Blk<T> fill_value(const FillIn& q) {
+// 1/sqrt(x) for x > 0 to a few units in the last place: the hardware
+// estimate refined by two Newton steps
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
+template <typename T, int S>
+__device__ __forceinline__ Blk<T> fill_value(FillIn q) {
   const int4 r = q.r;
   const bool dg = r.w & 1;
   if (r.x < 0 && !dg) return {T(0), T(0), T(0), T(0)};
+  if (S == 1 && !dg) q.x[4] = rsqrt_nr(q.x[2] * q.x[2] + q.x[3] * q.x[3]);
   J4 x = dg ? jac_diag(q.g, q.b, q.x[0], q.x[1], q.x[2], q.x[3], q.x[4], q.x[5])
             : jac_off(q.g, q.b, q.x[0], q.x[1], q.x[2], q.x[3], q.x[4]);
   if (r.w & 2) { x.v[2] = 0.0; x.v[3] = 0.0; }
@@ -484,7 +497,7 @@ __device__ __forceinline__ void phase_fill(const Sym& m, const Dims& D, St<T>& c
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int idx = base + u * nt;
-      if (idx < N) st_blk(c.lu + sB<S>(idx / S, idx % S), fill_value<T>(q[u]));
+      if (idx < N) st_blk(c.lu + sB<S>(idx / S, idx % S), fill_value<T, S>(q[u]));
     }
   }
   __syncthreads();
