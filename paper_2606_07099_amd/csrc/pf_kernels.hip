@@ -225,7 +225,7 @@ struct FillIn {
   double x[6];      // diagonal: e f |V| 1/|V| I_re I_im of the bus; else e f of the row bus, e f 1/|V| of the column bus
 };
 
-template <typename T, int S>
+template <typename T, int S, bool RES>
 __device__ __forceinline__ void fill_gather(const Sym& m, const St<T>& c, int s, FillIn& q) {
   const int4 r = q.r;
   const bool dg = r.w & 1;
@@ -234,7 +234,7 @@ __device__ __forceinline__ void fill_gather(const Sym& m, const St<T>& c, int s,
   const int is = c.g(r.y, s), ms = c.g(r.z, s);
   // one-scenario slices skip the gathers of fill-in positions (no value);
   // in wider slices the masked loads cost more than the lines they save
-  const bool fill_in = S == 1 && r.x < 0 && !dg;
+  const bool fill_in = !RES && S == 1 && r.x < 0 && !dg;
   q.x[0] = fill_in ? 0.0 : c.e[is];
   q.x[1] = fill_in ? 0.0 : c.f[is];
   if (dg) {
@@ -242,10 +242,10 @@ __device__ __forceinline__ void fill_gather(const Sym& m, const St<T>& c, int s,
   } else {
     q.x[2] = fill_in ? 0.0 : c.e[ms];
     q.x[3] = fill_in ? 0.0 : c.f[ms];
-    // one-scenario slices form the column bus's 1/|V| from its e and f
-    // (hardware estimate and two Newton steps) instead of gathering a third
-    // line per block; wider slices read it with the others
-    q.x[4] = S == 1 ? 0.0 : c.rvm[ms];
+    // with the state in HBM the column bus's 1/|V| is formed from its e and
+    // f (hardware estimate and two Newton steps) instead of gathering a third
+    // value per block (in LDS the gather is the cheaper)
+    q.x[4] = RES ? c.rvm[ms] : 0.0;
     q.x[5] = 0.0;
   }
 }
@@ -259,12 +259,12 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
-template <typename T, int S>
+template <typename T, bool RES>
 __device__ __forceinline__ Blk<T> fill_value(FillIn q) {
   const int4 r = q.r;
   const bool dg = r.w & 1;
   if (r.x < 0 && !dg) return {T(0), T(0), T(0), T(0)};
-  if (S == 1 && !dg) q.x[4] = rsqrt_nr(q.x[2] * q.x[2] + q.x[3] * q.x[3]);
+  if (!RES && !dg) q.x[4] = rsqrt_nr(q.x[2] * q.x[2] + q.x[3] * q.x[3]);
   J4 x = dg ? jac_diag(q.g, q.b, q.x[0], q.x[1], q.x[2], q.x[3], q.x[4], q.x[5])
             : jac_off(q.g, q.b, q.x[0], q.x[1], q.x[2], q.x[3], q.x[4]);
   if (r.w & 2) { x.v[2] = 0.0; x.v[3] = 0.0; }
@@ -481,8 +481,9 @@ __device__ __forceinline__ void wave_order() {
 
 // Jacobian values of every block of the pattern (fill-in blocks zeroed) for
 // the S scenarios: independent work, one pass before the factorisation.
-template <typename T, int S, int NB>
+template <typename T, int S, bool RES>
 __device__ __forceinline__ void phase_fill(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
+  constexpr int NB = RES ? 4 : 2;
   // NB blocks per thread have their gathers in flight together
   const int N = D.nnzb * S;
   for (int base = tid; base < N; base += NB * nt) {
@@ -493,11 +494,11 @@ __device__ __forceinline__ void phase_fill(const Sym& m, const Dims& D, St<T>& c
       q[u].r = idx < N ? m.fill4[idx / S] : make_int4(-1, 0, 0, 0);
     }
 #pragma unroll
-    for (int u = 0; u < NB; ++u) fill_gather<T, S>(m, c, (base + u * nt) % S, q[u]);
+    for (int u = 0; u < NB; ++u) fill_gather<T, S, RES>(m, c, (base + u * nt) % S, q[u]);
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int idx = base + u * nt;
-      if (idx < N) st_blk(c.lu + sB<S>(idx / S, idx % S), fill_value<T, S>(q[u]));
+      if (idx < N) st_blk(c.lu + sB<S>(idx / S, idx % S), fill_value<T, RES>(q[u]));
     }
   }
   __syncthreads();
@@ -1515,7 +1516,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
     }
     if (kp.mode == MODE_EVAL_MISMATCH || kp.mode == MODE_EVAL_FACTOR) break;
     if (kp.mode == MODE_EVAL_FILL) {
-      phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
+      phase_fill<T, S, RES>(m, D, c, tid, nt);
       break;
     }
     if (!act) break;
@@ -1523,7 +1524,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
     // as they write them; a slice of one scenario scatters each of those
     // stores to its own line, on the critical path of a level, so it updates
     // dx in a streaming pass of its own
-    phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
+    phase_fill<T, S, RES>(m, D, c, tid, nt);
     pc.mark(PH_FILL);
     pc.count(PH_NEWTON_STEPS);
     phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, true, piv, stg);
@@ -1668,7 +1669,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
   const bool keep = (kp.mode == MODE_SOLVE && kp.keep) || kp.mode == MODE_EVAL_FACTOR;
   if (keep) {
     if (tid < S) piv[tid] = 0;
-    phase_fill<T, S, RES ? 4 : 2>(m, D, c, tid, nt);
+    phase_fill<T, S, RES>(m, D, c, tid, nt);
     phase_factor<T, S, RES>(m, D, c, tid, nt, gmin, false, piv, stg);
     if constexpr (RES) {
       if (wv < S) {
