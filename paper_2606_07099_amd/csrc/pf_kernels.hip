@@ -238,7 +238,11 @@ __device__ __forceinline__ void fill_gather(const Sym& m, const St<T>& c, int s,
   q.x[0] = fill_in ? 0.0 : c.e[is];
   q.x[1] = fill_in ? 0.0 : c.f[is];
   if (dg) {
-    q.x[2] = c.vm[is]; q.x[3] = c.rvm[is]; q.x[4] = c.ire[is]; q.x[5] = c.iim[is];
+    // (with the state in HBM |V| and 1/|V| are formed from e and f, below)
+    q.x[2] = RES ? c.vm[is] : 0.0;
+    q.x[3] = RES ? c.rvm[is] : 0.0;
+    q.x[4] = c.ire[is];
+    q.x[5] = c.iim[is];
   } else {
     q.x[2] = fill_in ? 0.0 : c.e[ms];
     q.x[3] = fill_in ? 0.0 : c.f[ms];
@@ -265,6 +269,11 @@ __device__ __forceinline__ Blk<T> fill_value(FillIn q) {
   const bool dg = r.w & 1;
   if (r.x < 0 && !dg) return {T(0), T(0), T(0), T(0)};
   if (!RES && !dg) q.x[4] = rsqrt_nr(q.x[2] * q.x[2] + q.x[3] * q.x[3]);
+  if (!RES && dg) {
+    const double v2 = q.x[0] * q.x[0] + q.x[1] * q.x[1];
+    q.x[3] = rsqrt_nr(v2);
+    q.x[2] = v2 * q.x[3];
+  }
   J4 x = dg ? jac_diag(q.g, q.b, q.x[0], q.x[1], q.x[2], q.x[3], q.x[4], q.x[5])
             : jac_off(q.g, q.b, q.x[0], q.x[1], q.x[2], q.x[3], q.x[4]);
   if (r.w & 2) { x.v[2] = 0.0; x.v[3] = 0.0; }
