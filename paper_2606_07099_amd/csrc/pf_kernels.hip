@@ -1295,7 +1295,8 @@ __device__ __forceinline__ void rt_bsolve(const Sym& m, const Dims& D, St<T>& c,
 
 // dV = V (d|V|/|V| + j dtheta) for the correction dx (slack: 0); four items
 // per thread, loads first
-template <typename T, int S>
+// (with the state in HBM, 1/|V| is formed from e and f: one stream fewer)
+template <typename T, int S, bool RES>
 __device__ __forceinline__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
   constexpr int U = 4;
   const int s = tid % S, N = D.n_bus * S;
@@ -1312,7 +1313,7 @@ __device__ __forceinline__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, 
       const int go = c.g(o / S, s);
       dth[u] = c.dx[sP<S>(pa, s)];
       dvm[u] = c.dx[sP<S>(pa, s) + 1];
-      rv[u] = c.rvm[go];
+      rv[u] = RES ? c.rvm[go] : 0.0;
       e[u] = c.e[go];
       f[u] = c.f[go];
     }
@@ -1322,6 +1323,7 @@ __device__ __forceinline__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, 
       if (idx >= N) continue;
       double dvr = 0.0, dvi = 0.0;
       if (a[u] >= 0) {
+        if (!RES) rv[u] = rsqrt_nr(e[u] * e[u] + f[u] * f[u]);
         const double rho = bt[u] == 0 ? dvm[u] * rv[u] : 0.0;
         dvr = e[u] * rho - f[u] * dth[u];
         dvi = f[u] * rho + e[u] * dth[u];
@@ -1402,7 +1404,9 @@ struct GenW {
 };
 
 // e + jf from (|V|, theta) for the scenarios in `mask`
-template <typename T, int S>
+// (1/|V| is stored only for LDS-resident slices: the passes over HBM state
+// form it from e and f)
+template <typename T, int S, bool RES>
 __device__ __forceinline__ void phase_set_state(const Dims& D, St<T>& c, int tid, int nt, int mask) {
   for (int idx = tid; idx < D.n_bus * S; idx += nt) {
     if (!((mask >> (idx % S)) & 1)) continue;
@@ -1412,7 +1416,7 @@ __device__ __forceinline__ void phase_set_state(const Dims& D, St<T>& c, int tid
     const double v = c.vm[o];
     c.e[o] = v * cs;
     c.f[o] = v * sn;
-    c.rvm[o] = 1.0 / v;
+    if (RES) c.rvm[o] = 1.0 / v;
   }
   __syncthreads();
 }
@@ -1485,7 +1489,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
     }
   }
   __syncthreads();
-  phase_set_state<T, S>(D, c, tid, nt, (1 << S) - 1);
+  phase_set_state<T, S, RES>(D, c, tid, nt, (1 << S) - 1);
 
   const bool mixed = sizeof(T) == 4;
   const int gmin = kp.gmin > S ? kp.gmin : S;
@@ -1571,7 +1575,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       int ref = act;   // scenarios still refining their correction
       for (int r = 0; r < kp.refine; ++r) {
         pc.mark(PH_OTHER);
-        phase_dv<T, S>(m, D, c, tid, nt);
+        phase_dv<T, S, RES>(m, D, c, tid, nt);
         pc.mark(PH_REFINE_DV);
         phase_residual<T, S>(m, D, c, tid, nt, kp.adaptive, scr);
         pc.mark(PH_REFINE_RESIDUAL);
@@ -1625,7 +1629,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       sincos(va, &sn, &cs);
       c.e[o] = vm * cs;
       c.f[o] = vm * sn;
-      c.rvm[o] = 1.0 / vm;
+      if (RES) c.rvm[o] = 1.0 / vm;
     }
     __syncthreads();
     if (tid < S && ((act >> tid) & 1)) s_it[tid]++;
