@@ -560,7 +560,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
     }
     // the adjoint reads this slice workspace in place
     t->adj_slice = -sl;
-    t->adj_nt = std::min(512, std::max(256, 64 * sl));
+    t->adj_nt = 1024;   // as the Newton kernel: more lanes per level of the transposed solves
     t->adj_lds = t->lds_bytes;
     // a full workgroup of 16 wavefronts: measured fastest for every slice
     // width (more lanes per level of the elimination schedule)

@@ -146,9 +146,9 @@ inline int res_newton_threads(bool) { return kResThreads; }
 // slice = scenarios per workgroup: 1, 2 or 4 when LDS-resident, up to 16 otherwise.
 hipError_t launch_newton(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds,
                          bool lds_res, hipStream_t st);
-// slice > 0: LDS-resident adjoint slices of that width (256 threads);
+// slice > 0: LDS-resident adjoint slices of that width (kResThreads threads);
 // slice < 0: HBM-resident slices of width -slice reading the forward solve's
-// slice workspace (at most 512 threads)
+// slice workspace (at most 1024 threads)
 hipError_t launch_adjoint(const KParams& kp, bool fp32, int slice, int grid, int nt, size_t lds, hipStream_t st);
 hipError_t launch_jacobian_dense(const KParams& kp, int grid, hipStream_t st);
 // Step-2 recovery of the generation block for kp.count scenarios

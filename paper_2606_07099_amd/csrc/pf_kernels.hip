@@ -1993,7 +1993,7 @@ __device__ __forceinline__ void phase_adj_residual_s(const Sym& m, const Dims& D
 }
 
 template <typename T, bool RES, int S>
-__global__ void __launch_bounds__(RES ? kResThreads : 512) k_adjoint_slice(KParams kp) {
+__global__ void __launch_bounds__(RES ? kResThreads : 1024) k_adjoint_slice(KParams kp) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int slice = blockIdx.x;
@@ -2292,7 +2292,7 @@ static hipError_t launch_adjoint_t(const KParams& kp, int slice, int grid, int n
 
 template <typename T>
 static hipError_t launch_adjoint_hbm_t(const KParams& kp, int slice, int grid, int nt, size_t lds, hipStream_t st) {
-  if (nt > 512) return hipErrorInvalidValue;
+  if (nt > 1024) return hipErrorInvalidValue;
   switch (slice) {
     case 1: hipLaunchKernelGGL((k_adjoint_slice<T, false, 1>), dim3(grid), dim3(nt), lds, st, kp); break;
     case 2: hipLaunchKernelGGL((k_adjoint_slice<T, false, 2>), dim3(grid), dim3(nt), lds, st, kp); break;
