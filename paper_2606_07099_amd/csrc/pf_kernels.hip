@@ -2016,6 +2016,9 @@ __global__ void __launch_bounds__(RES ? kResThreads : 1024) k_adjoint_slice(KPar
   } else {
     c = bind_state<T, S>(kp.wsl_d + (size_t)slice * S * kp.lay.sd,
                          reinterpret_cast<T*>(kp.wsl_t) + (size_t)slice * S * kp.lay.st, kp.lay);
+    // the solve vector in LDS where the Newton kernel keeps it there too (the
+    // workgroup has the same LDS)
+    if (kp.dims.y_lds_off) c.y = reinterpret_cast<T*>(smem + kp.dims.y_lds_off);
   }
   const int n = D.n_bus, nb = D.nb;
   const bool eval = kp.mode == MODE_EVAL_ADJOINT;
