@@ -52,15 +52,15 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # the kernel sources they were taken on; a changed kernel reports null.
 # Sources: profiles/*_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "273fdad700f8a95fce1ffcf8834e0c844ff427540d3a4e70e1cf1fd64cb7951f": {
-        "c1/mixed": 7024313,
-        "c1/fp64": 6926016,
-        "c2/mixed": 46056349581,
-        "c2/fp64": 48900603732,
-        "c3/mixed": 3401512094,
-        "c3/fp64": 3613741311,
-        "c4/mixed": 49551544488,
-        "c4/fp64": 50563092537,
+    "7e44cad7fc2f92e95d596b2a56834160f40fb2c88bb21a4d3872ccffb0f8bd34": {
+        "c1/mixed": 7019174,
+        "c1/fp64": 6937261,
+        "c2/mixed": 43769766120,
+        "c2/fp64": 46887935300,
+        "c3/mixed": 3121995646,
+        "c3/fp64": 3441287149,
+        "c4/mixed": 39277912013,
+        "c4/fp64": 41196989244,
     },
 }
 
