@@ -1567,14 +1567,26 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
     pc.mark(PH_BSOLVE_TAIL);
     phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg, dx_set);   // dx = y as well
     pc.mark(PH_BSOLVE_LEVELS);
-    if (!fuse) {
-      for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
-      __syncthreads();
-    }
+    // slices that keep dx out of the backward solves hand the last solve's
+    // y to dx only when a later pass reads dx: the state update reads dx
+    // (pend 0), y (pend 1: dx = y) or dx + y (pend 2, scenarios in pmask)
+    int pend = fuse ? 0 : 1, pmask = 0;
+    auto settle = [&]() {
+      if (pend == 1) {
+        for (int q = tid; q < 2 * nb * S; q += nt) c.dx[q] = double(c.y[q]);
+        __syncthreads();
+      } else if (pend == 2) {
+        for (int q = tid; q < 2 * nb * S; q += nt)
+          if ((pmask >> ((q >> 1) % S)) & 1) c.dx[q] += double(c.y[q]);
+        __syncthreads();
+      }
+      pend = 0;
+    };
     if (mixed) {
       int ref = act;   // scenarios still refining their correction
       for (int r = 0; r < kp.refine; ++r) {
         pc.mark(PH_OTHER);
+        settle();
         phase_dv<T, S, RES>(m, D, c, tid, nt);
         pc.mark(PH_REFINE_DV);
         phase_residual<T, S>(m, D, c, tid, nt, kp.adaptive, scr);
@@ -1605,13 +1617,15 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
         phase_solve<T, S, RES, false>(m, D, c, tid, nt, gmin, stg, dx_add, ref);   // dx += y as well
         pc.mark(PH_REFINE_BSOLVE_LEVELS);
         if (!fuse) {
-          for (int q = tid; q < 2 * nb * S; q += nt)
-            if ((ref >> ((q >> 1) % S)) & 1) c.dx[q] += double(c.y[q]);
-          __syncthreads();
+          pend = 2;
+          pmask = ref;
         }
       }
     }
-    if (kp.mode == MODE_EVAL_STEP) break;
+    if (kp.mode == MODE_EVAL_STEP) {
+      settle();
+      break;
+    }
     // state update of the active scenarios (theta on non-slack buses, |V| on
     // PQ buses) and their e + jf, by the thread that owns the item in both
     for (int idx = tid; idx < n * S; idx += nt) {
@@ -1620,8 +1634,12 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
       const int a = m.bus_blk[i], o = c.g(i, s);
       double va = c.va[idx], vm = c.vm[o];
       if (a >= 0) {
-        va += c.dx[sP<S>(a, s)];
-        if (m.bus_type[i] == 0) vm += c.dx[sP<S>(a, s) + 1];
+        const int p = sP<S>(a, s);
+        const bool with_y = pend == 1 || (pend == 2 && ((pmask >> s) & 1));
+        const double d0 = (pend == 1 ? 0.0 : c.dx[p]) + (with_y ? double(c.y[p]) : 0.0);
+        const double d1 = (pend == 1 ? 0.0 : c.dx[p + 1]) + (with_y ? double(c.y[p + 1]) : 0.0);
+        va += d0;
+        if (m.bus_type[i] == 0) vm += d1;
         c.va[idx] = va;
         c.vm[o] = vm;
       }
