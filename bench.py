@@ -52,15 +52,15 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # the kernel sources they were taken on; a changed kernel reports null.
 # Sources: profiles/*_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "7e44cad7fc2f92e95d596b2a56834160f40fb2c88bb21a4d3872ccffb0f8bd34": {
-        "c1/mixed": 7019174,
-        "c1/fp64": 6937261,
-        "c2/mixed": 43769766120,
-        "c2/fp64": 46887935300,
-        "c3/mixed": 3121995646,
-        "c3/fp64": 3441287149,
-        "c4/mixed": 39277912013,
-        "c4/fp64": 41196989244,
+    "aab1857f4997a2c42a355b4c4d22ce425821cd4e197b1eb37b55441a4b986378": {
+        "c1/mixed": 7029432,
+        "c1/fp64": 6922926,
+        "c2/mixed": 43785740029,
+        "c2/fp64": 46721443074,
+        "c3/mixed": 3125333802,
+        "c3/fp64": 3446849594,
+        "c4/mixed": 38553863591,
+        "c4/fp64": 40970650840,
     },
 }
 
