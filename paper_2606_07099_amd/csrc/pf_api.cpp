@@ -474,8 +474,7 @@ int pf_template_build(int32_t n_bus, const int32_t* bus_type, const int32_t* y_i
   so.tt_ptr = (int)pk.add(chunks.tt_ptr); so.tt_pairs = (int)pk.add(chunks.tt_pairs);
   so.y_tr = (int)pk.add(S.y_tr);
   so.adj_bytes = (int)pk.align();
-  so.tail_cblk = (int)pk.add(S.tail_cblk); so.tail_lbase = (int)pk.add(S.tail_lbase);
-  so.tail_cpos = (int)pk.add(S.tail_cpos);
+  so.tail_cblk = (int)pk.add(S.tail_cblk);
   so.tail_prog = (int)pk.add(S.tail_prog);
   so.ord_p = (int)pk.add(ord_p); so.ord_q = (int)pk.add(ord_q);
   so.total_bytes = (int)pk.align();

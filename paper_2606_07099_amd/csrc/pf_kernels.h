@@ -70,7 +70,7 @@ struct SymOffsets {
   // [newton_bytes, adj_bytes): what the LDS-resident adjoint reads besides
   int ut_ptr, ut_blob, lt_ptr, lt_blob, tt_ptr, tt_pairs, y_tr;
   int adj_bytes;
-  int tail_cblk, tail_lbase, tail_cpos;   // compact tail numbering (LDS copy of the tail)
+  int tail_cblk;                          // position of each compact tail block (LDS copy of the tail)
   int tail_prog;                          // per-pivot elimination program of the tail (LDS tail copy)
   int ord_p, ord_q;                       // paper-order positions (exports)
   int total_bytes;

@@ -126,7 +126,7 @@ struct Sym {
   const unsigned* tail_mask;
   const int *y_tr, *ord_p, *ord_q;
   const int *f_ptr, *f_blob, *fs_ptr, *fs_blob, *bs_ptr, *bs_blob;
-  const int *tail_cblk, *tail_lbase, *tail_cpos;
+  const int* tail_cblk;
 };
 
 __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned char* g,
@@ -157,8 +157,6 @@ __device__ __forceinline__ Sym bind_sym(const unsigned char* nb, const unsigned 
   m.ord_p = I(g, o.ord_p);
   m.ord_q = I(g, o.ord_q);
   m.tail_cblk = I(g, o.tail_cblk);
-  m.tail_lbase = I(g, o.tail_lbase);
-  m.tail_cpos = I(g, o.tail_cpos);
   return m;
 }
 
