@@ -890,13 +890,24 @@ __device__ __forceinline__ const int* ltail_updates(const Sym& m, const Dims& D,
 // sums meeting by a lane swap); the result stays in y0, y1
 template <typename T, int S>
 __device__ __forceinline__ void ltail_fs_one(const Sym& m, const Dims& D, St<T>& c, const T* tl, const int* tq,
-                                             int s, int l, T& y0, T& y1) {
+                                             int s, int l, T& y0, T& y1, const T* pa = nullptr, int P = 0) {
   const int t = D.tail_t, tb = D.tail_base, nbs = D.tail_nbs;
   const int lr = l & 31, hs = l >> 5;
   T o0 = T(0), o1 = T(0);
   y0 = T(0);
   y1 = T(0);
-  if (lr < t) {
+  if (pa) {
+    // the terms were summed by the whole workgroup: P parts per row, added
+    // in part order by lane l (lanes l + 32 add nothing)
+    if (l < t) {
+      y0 = c.y[sP<S>(tb + l, s)];
+      y1 = c.y[sP<S>(tb + l, s) + 1];
+      for (int h = 0; h < P; ++h) {
+        o0 += pa[((s * t + l) * P + h) * 2];
+        o1 += pa[((s * t + l) * P + h) * 2 + 1];
+      }
+    }
+  } else if (lr < t) {
     const int a = tb + lr;
     if (hs == 0) {
       y0 = c.y[sP<S>(a, s)];
@@ -922,8 +933,10 @@ __device__ __forceinline__ void ltail_fs_one(const Sym& m, const Dims& D, St<T>&
       }
     }
   }
-  o0 += __shfl_xor(o0, 32);
-  o1 += __shfl_xor(o1, 32);
+  if (!pa) {
+    o0 += __shfl_xor(o0, 32);
+    o1 += __shfl_xor(o1, 32);
+  }
   y0 -= o0;
   y1 -= o1;
   unsigned mk = l < t ? (unsigned)tq[8 * l + 5] : 0u;
@@ -1026,16 +1039,46 @@ __device__ __forceinline__ void ltail_bsolve(const Dims& D, St<T>& c, const T* t
 }
 
 // forward then backward solve of the tail rows (refinement), the forward
-// result kept in registers
+// result kept in registers.  With more wavefronts than scenarios the terms
+// of the tail rows on rows outside the tail are summed by the whole
+// workgroup first: thread (scenario, row l, part h) adds entries h, h + P,
+// ... of row l, and its sum lands in LDS (pa, the metadata area, free here)
 template <typename T, int S>
 __device__ __forceinline__ void ltail_fbsolve(const Sym& m, const Dims& D, St<T>& c, const T* tl, const T* td,
-                                              const int* tq, int tid, int nt, int dxmode, int mask) {
+                                              const int* tq, int tid, int nt, int dxmode, int mask,
+                                              unsigned char* stg) {
   const int w = tid >> 6, l = tid & 63, nw = nt >> 6;
+  const int t = D.tail_t;
+  T* pa = nullptr;
+  int P = 0;
+  if (S < nw && t > 0) {
+    P = nt / (S * t);
+    const int cap = (int)((4 * (size_t)D.chunk_ints) / (2 * sizeof(T) * S * t));
+    P = P < cap ? P : cap;
+    P = P < 32 ? P : 32;
+    if (P >= 8) {   // (a few parts per row gain nothing: measured with slices of 8)
+      pa = reinterpret_cast<T*>(stg);
+      for (int q = tid; q < S * t * P; q += nt) {
+        const int h = q % P, lr = (q / P) % t, s = q / (P * t);
+        const int a = D.tail_base + lr;
+        T o0 = T(0), o1 = T(0);
+        for (int p = m.rp[a] + h; p < m.tail_split[lr]; p += P) {
+          const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
+          const int k = m.ci[p];
+          o0 += L.a * c.y[sP<S>(k, s)] + L.b * c.y[sP<S>(k, s) + 1];
+          o1 += L.c * c.y[sP<S>(k, s)] + L.d * c.y[sP<S>(k, s) + 1];
+        }
+        pa[((s * t + lr) * P + h) * 2] = o0;
+        pa[((s * t + lr) * P + h) * 2 + 1] = o1;
+      }
+      __syncthreads();
+    }
+  }
   for (int s = w; s < S; s += nw) {
     T y0, y1;
     double dx0, dx1;
     ltail_dx<T, S>(D, c, s, l, dxmode, dx0, dx1);
-    ltail_fs_one<T, S>(m, D, c, tl, tq, s, l, y0, y1);
+    ltail_fs_one<T, S>(m, D, c, tl, tq, s, l, y0, y1, pa, P);
     ltail_bs_one<T, S>(D, tl, td, tq, s, l, y0, y1);
     ltail_put<T, S>(D, c, s, l, y0, y1, dxmode, mask, dx0, dx1);
   }
@@ -1608,7 +1651,7 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
             rt_bsolve<T, S>(m, D, c, wv, ln, R, dx_add, ref);
           }
         } else {
-          ltail_fbsolve<T, S>(m, D, c, tl, td, tq, tid, nt, dx_add, ref);
+          ltail_fbsolve<T, S>(m, D, c, tl, td, tq, tid, nt, dx_add, ref, stg);
         }
         __syncthreads();
         pc.mark(PH_REFINE_TAIL);
