@@ -52,15 +52,15 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # the kernel sources they were taken on; a changed kernel reports null.
 # Sources: profiles/*_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "aab1857f4997a2c42a355b4c4d22ce425821cd4e197b1eb37b55441a4b986378": {
-        "c1/mixed": 7029432,
-        "c1/fp64": 6922926,
-        "c2/mixed": 43785740029,
-        "c2/fp64": 46721443074,
-        "c3/mixed": 3125333802,
-        "c3/fp64": 3446849594,
-        "c4/mixed": 38553863591,
-        "c4/fp64": 40970650840,
+    "4a69fa784a78c1f31221fe8cce5b4f2933e8fd4c72ddfd89c56c2c831491e33d": {
+        "c1/mixed": 7014073,
+        "c1/fp64": 6928046,
+        "c2/mixed": 43792713649,
+        "c2/fp64": 46687346024,
+        "c3/mixed": 3138585683,
+        "c3/fp64": 3447556101,
+        "c4/mixed": 38576440962,
+        "c4/fp64": 41014034851,
     },
 }
 
