@@ -1039,10 +1039,12 @@ __device__ __forceinline__ void ltail_bsolve(const Dims& D, St<T>& c, const T* t
 }
 
 // forward then backward solve of the tail rows (refinement), the forward
-// result kept in registers.  With more wavefronts than scenarios the terms
-// of the tail rows on rows outside the tail are summed by the whole
-// workgroup first: thread (scenario, row l, part h) adds entries h, h + P,
-// ... of row l, and its sum lands in LDS (pa, the metadata area, free here)
+// result kept in registers.  The terms of the tail rows on rows outside the
+// tail are summed by the whole workgroup first: thread (row l, part h,
+// scenario s), scenarios fastest, so that the lanes of a wavefront read the
+// slice's interleaved blocks and unknowns in contiguous runs, adds entries
+// h, h + P, ... of row l (four in flight), and its sum lands in LDS (pa, the
+// metadata area, free here); the row's lane adds the parts in order
 template <typename T, int S>
 __device__ __forceinline__ void ltail_fbsolve(const Sym& m, const Dims& D, St<T>& c, const T* tl, const T* td,
                                               const int* tq, int tid, int nt, int dxmode, int mask,
@@ -1051,22 +1053,35 @@ __device__ __forceinline__ void ltail_fbsolve(const Sym& m, const Dims& D, St<T>
   const int t = D.tail_t;
   T* pa = nullptr;
   int P = 0;
-  if (S < nw && t > 0) {
+  if (t > 0) {
     P = nt / (S * t);
     const int cap = (int)((4 * (size_t)D.chunk_ints) / (2 * sizeof(T) * S * t));
     P = P < cap ? P : cap;
     P = P < 32 ? P : 32;
-    if (P >= 8) {   // (a few parts per row gain nothing: measured with slices of 8)
+    if (P >= 1) {
       pa = reinterpret_cast<T*>(stg);
       for (int q = tid; q < S * t * P; q += nt) {
-        const int h = q % P, lr = (q / P) % t, s = q / (P * t);
+        const int s = q % S, h = (q / S) % P, lr = q / (S * P);
         const int a = D.tail_base + lr;
+        const int p1 = m.tail_split[lr];
         T o0 = T(0), o1 = T(0);
-        for (int p = m.rp[a] + h; p < m.tail_split[lr]; p += P) {
-          const Blk<T> L = ld_blk(c.lu + sB<S>(p, s));
-          const int k = m.ci[p];
-          o0 += L.a * c.y[sP<S>(k, s)] + L.b * c.y[sP<S>(k, s) + 1];
-          o1 += L.c * c.y[sP<S>(k, s)] + L.d * c.y[sP<S>(k, s) + 1];
+        for (int p = m.rp[a] + h; p < p1; p += 4 * P) {
+          Blk<T> L[4];
+          T z[4][2];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int pu = p + u * P;
+            const bool in = pu < p1;
+            const int k = in ? m.ci[pu] : 0;
+            L[u] = in ? ld_blk(c.lu + sB<S>(pu, s)) : Blk<T>{T(0), T(0), T(0), T(0)};
+            z[u][0] = c.y[sP<S>(k, s)];
+            z[u][1] = c.y[sP<S>(k, s) + 1];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            o0 += L[u].a * z[u][0] + L[u].b * z[u][1];
+            o1 += L[u].c * z[u][0] + L[u].d * z[u][1];
+          }
         }
         pa[((s * t + lr) * P + h) * 2] = o0;
         pa[((s * t + lr) * P + h) * 2 + 1] = o1;
