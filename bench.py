@@ -52,15 +52,15 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # the kernel sources they were taken on; a changed kernel reports null.
 # Sources: profiles/*_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "4a69fa784a78c1f31221fe8cce5b4f2933e8fd4c72ddfd89c56c2c831491e33d": {
-        "c1/mixed": 7014073,
-        "c1/fp64": 6928046,
-        "c2/mixed": 43792713649,
-        "c2/fp64": 46687346024,
-        "c3/mixed": 3138585683,
-        "c3/fp64": 3447556101,
-        "c4/mixed": 38576440962,
-        "c4/fp64": 41014034851,
+    "2496cb9f736513c87968869f881e1a103ccd8b1d6b2245339453266894730bfb": {
+        "c1/mixed": 7003834,
+        "c1/fp64": 6927040,
+        "c2/mixed": 43784522274,
+        "c2/fp64": 46685093224,
+        "c3/mixed": 3122517971,
+        "c3/fp64": 3449529726,
+        "c4/mixed": 38574117049,
+        "c4/fp64": 41015314949,
     },
 }
 
