@@ -2133,16 +2133,20 @@ __global__ void __launch_bounds__(RES ? kResThreads : 1024) k_adjoint_slice(KPar
     s_ok[tid] = b < kp.count && kp.ws_i[(size_t)b * 4] == 0;
   }
   __syncthreads();
-  // I at the kept state, g_z1 per block into F
+  // I at the kept state (HBM-resident slices: the forward kernel's last
+  // mismatch left it in the slice workspace, at the same state), g_z1 per
+  // block into F
   for (int idx = tid; idx < n * S; idx += nt) {
     const int i = idx / S, s = idx % S;
     const int b = slice * S + s;
-    double ir[1], ii[1];
-    const int ib[1] = {i};
-    const bool vb[1] = {true};
-    yrow_multi<S, 1, 4>(m, c.e, c.f, c.gs, ib, s, vb, ir, ii);
-    c.ire[c.g(i, s)] = ir[0];
-    c.iim[c.g(i, s)] = ii[0];
+    if (RES) {
+      double ir[1], ii[1];
+      const int ib[1] = {i};
+      const bool vb[1] = {true};
+      yrow_multi<S, 1, 4>(m, c.e, c.f, c.gs, ib, s, vb, ir, ii);
+      c.ire[c.g(i, s)] = ir[0];
+      c.iim[c.g(i, s)] = ii[0];
+    }
     const int a = m.bus_blk[i];
     if (a < 0) continue;
     double g0 = 0.0, g1 = 0.0;
