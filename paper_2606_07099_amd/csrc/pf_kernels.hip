@@ -794,6 +794,14 @@ __device__ __forceinline__ void ltail_store_dinv(const Dims& D, St<T>& c, const 
   }
 }
 
+template <typename T, int S>
+__device__ __forceinline__ void ltail_load_dinv(const Dims& D, St<T>& c, T* td, int tid, int nt) {
+  for (int q = tid; q < D.tail_t * S * 4; q += nt) {
+    const int comp = q & 3, s = (q >> 2) % S, k = (q >> 2) / S;
+    td[tdB(k, s, D.tail_t) + comp] = c.dinv[sB<S>(D.tail_base + k, s) + comp];
+  }
+}
+
 // ty: the tail rows' right-hand sides for the fused forward solve, written
 // back at the end.  Every lane inverts the pivot block itself from its LDS
 // copy (a broadcast read); the updates of one pivot have distinct targets
@@ -1917,8 +1925,14 @@ __device__ __forceinline__ void phase_tsolve(const AdjSym& a, const Dims& D, St<
 // column h of the stored block (j, l) (U_jl^T left of the diagonal, the
 // transposed inverted pivot on it, L_jl^T right of it).  U^T forward (after
 // the terms on rows outside the tail), then L^T backward.
+// With tl (HBM-resident slices) the tail blocks come from the LDS tail copy
+// (tl, td, located through the tail program's records tq) instead of the
+// slice workspace, and the terms on rows outside the tail from the parts pa
+// (P per row) the whole workgroup summed beforehand.
 template <typename T, int S>
-__device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const Dims& D, St<T>& c, int s, int ln) {
+__device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const Dims& D, St<T>& c, int s, int ln,
+                                          const T* tl = nullptr, const T* td = nullptr, const int* tq = nullptr,
+                                          const T* pa = nullptr, int P = 0) {
   const int t = __builtin_amdgcn_readfirstlane(D.tail_t), tb = D.tail_base;
   if (t == 0) return;
   const int l = lane_row(ln), h = ln & 1;
@@ -1932,21 +1946,42 @@ __device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const D
     for (int u = 0; u < 8; ++u) {
       const int j = jb + u;
       p[u] = -1;
-      if (j < t && l < t) p[u] = j == l ? -2 : m.tail_pos[j * t + l];
+      if (j < t && l < t) {
+        if (j == l) {
+          p[u] = -2;
+        } else if (tl) {
+          // compact index of block (j, l): row j's blocks are consecutive
+          // in column order, located by its masks
+          const int dk = tq[8 * j];
+          const unsigned lm = (unsigned)tq[8 * j + 5], um = (unsigned)tq[8 * j + 6];
+          const unsigned below = (1u << l) - 1u;
+          if (j < l && ((um >> l) & 1u)) p[u] = dk + 1 + __popc(um & below);
+          else if (j > l && ((lm >> l) & 1u)) p[u] = dk - __popc(lm) + __popc(lm & below);
+        } else {
+          p[u] = m.tail_pos[j * t + l];
+        }
+      }
     }
     T x0[8], x1[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       x0[u] = T(0);
       x1[u] = T(0);
-      const T* b = p[u] == -2 ? c.dinv + sB<S>(tb + l, s) : (p[u] >= 0 ? c.lu + sB<S>(p[u], s) : nullptr);
+      const T* b = nullptr;
+      if (tl) b = p[u] == -2 ? td + tdB(l, s, t) : (p[u] >= 0 ? tl + tcB(p[u], s, D.tail_nbs) : nullptr);
+      else b = p[u] == -2 ? c.dinv + sB<S>(tb + l, s) : (p[u] >= 0 ? c.lu + sB<S>(p[u], s) : nullptr);
       if (b) { x0[u] = b[h]; x1[u] = b[2 + h]; }
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) { R.p[jb + u] = x0[u]; R.q[jb + u] = x1[u]; }
   }
   T y = T(0);
-  if (l < t) {
+  if (l < t && pa) {
+    y = c.y[sP<S>(tb + l, s) + h];
+    T acc = T(0);
+    for (int hp = 0; hp < P; ++hp) acc += pa[((s * t + l) * P + hp) * 2 + h];
+    y -= acc;
+  } else if (l < t) {
     const int row = tb + l;
     y = c.y[sP<S>(row, s) + h];
     // the terms on rows outside the tail, four pairs in flight
@@ -1991,6 +2026,53 @@ __device__ __forceinline__ void rt_tsolve(const Sym& m, const AdjSym& a, const D
     }
   }
   if (l < t) c.y[sP<S>(tb + l, s) + h] = y;
+}
+
+// HBM-resident adjoint slices: the terms of the tail rows of U^T on rows
+// outside the tail, summed by the whole workgroup before the tail solves
+// (thread (row l, part h, scenario s), scenarios fastest, adds pairs h,
+// h + P, ... of row l, four in flight) into LDS parts (lds, the metadata
+// area, free between the two transposed solves); returns the parts, P per
+// row, or nullptr when not even one part per row fits
+template <typename T, int S>
+__device__ __forceinline__ const T* tt_parts(const AdjSym& a, const Dims& D, St<T>& c, int tid, int nt,
+                                             unsigned char* lds, int& P) {
+  const int t = D.tail_t;
+  P = 0;
+  if (t == 0) return nullptr;
+  P = nt / (S * t);
+  const int cap = (int)((4 * (size_t)D.chunk_ints) / (2 * sizeof(T) * S * t));
+  P = P < cap ? P : cap;
+  P = P < 32 ? P : 32;
+  if (P < 1) return nullptr;
+  T* pa = reinterpret_cast<T*>(lds);
+  for (int q = tid; q < S * t * P; q += nt) {
+    const int s = q % S, h = (q / S) % P, lr = q / (S * P);
+    const int q1 = a.tt_ptr[lr + 1];
+    T o0 = T(0), o1 = T(0);
+    for (int p = a.tt_ptr[lr] + h; p < q1; p += 4 * P) {
+      Blk<T> B[4];
+      T z[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int pu = p + u * P;
+        const bool in = pu < q1;
+        const int k = in ? a.tt_pairs[2 * pu] : 0, mp = in ? a.tt_pairs[2 * pu + 1] : 0;
+        B[u] = in ? ld_blk(c.lu + sB<S>(mp, s)) : Blk<T>{T(0), T(0), T(0), T(0)};
+        z[u][0] = c.y[sP<S>(k, s)];
+        z[u][1] = c.y[sP<S>(k, s) + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        o0 += B[u].a * z[u][0] + B[u].c * z[u][1];
+        o1 += B[u].b * z[u][0] + B[u].d * z[u][1];
+      }
+    }
+    pa[((s * t + lr) * P + h) * 2] = o0;
+    pa[((s * t + lr) * P + h) * 2 + 1] = o1;
+  }
+  __syncthreads();
+  return pa;
 }
 
 // adjoint residual r = g - J1^T lam in FP64 without forming J1 (transposed
@@ -2128,6 +2210,19 @@ __global__ void __launch_bounds__(RES ? kResThreads : 1024) k_adjoint_slice(KPar
                              : ((comp == 0 || comp == 3) ? T(1) : T(0));
   }
   }
+  // HBM-resident slices: the factored tail in LDS, as the Newton kernel
+  // lays it out (the same LDS size), with the tail program's records
+  T* tl = nullptr;
+  T* td = nullptr;
+  int* tq = nullptr;
+  if constexpr (!RES) {
+    tl = reinterpret_cast<T*>(smem + kScratchBytes + 4 * (size_t)D.chunk_ints);
+    td = tl + (size_t)D.tail_nbs * S * 4;
+    tq = reinterpret_cast<int*>(td + (size_t)D.tail_t * S * 4 + (size_t)D.tail_t * S * 2);
+    for (int q = tid; q < D.tail_prog_prefix; q += nt) tq[q] = m.tail_prog[q];
+    ltail_copy<T, S>(m, D, c, tl, tid, nt, false);
+    ltail_load_dinv<T, S>(D, c, td, tid, nt);
+  }
   if (tid < S) {
     const int b = slice * S + tid;
     s_ok[tid] = b < kp.count && kp.ws_i[(size_t)b * 4] == 0;
@@ -2173,7 +2268,13 @@ __global__ void __launch_bounds__(RES ? kResThreads : 1024) k_adjoint_slice(KPar
   const int gmin = S > 4 ? S : 4;
   auto solve = [&]() {
     phase_tsolve<T, S, RES, true>(as, D, c, tid, nt, gmin, stg);
-    for (int s = wv; s < S; s += nw) rt_tsolve<T, S>(m, as, D, c, s, ln);
+    if constexpr (RES) {
+      for (int s = wv; s < S; s += nw) rt_tsolve<T, S>(m, as, D, c, s, ln);
+    } else {
+      int P = 0;
+      const T* pa = tt_parts<T, S>(as, D, c, tid, nt, stg, P);
+      for (int s = wv; s < S; s += nw) rt_tsolve<T, S>(m, as, D, c, s, ln, tl, td, tq, pa, P);
+    }
     __syncthreads();
     phase_tsolve<T, S, RES, false>(as, D, c, tid, nt, gmin, stg);
   };
