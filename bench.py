@@ -52,15 +52,15 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # the kernel sources they were taken on; a changed kernel reports null.
 # Sources: profiles/*_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "2496cb9f736513c87968869f881e1a103ccd8b1d6b2245339453266894730bfb": {
+    "d2ebf0b1ed812306880ff7a1f8bba5c0ab937c51e55c715e31663ba77cde723c": {
         "c1/mixed": 7003834,
-        "c1/fp64": 6927040,
-        "c2/mixed": 43784522274,
-        "c2/fp64": 46685093224,
-        "c3/mixed": 3122517971,
-        "c3/fp64": 3449529726,
-        "c4/mixed": 38574117049,
-        "c4/fp64": 41015314949,
+        "c1/fp64": 6927022,
+        "c2/mixed": 43781643922,
+        "c2/fp64": 46690417837,
+        "c3/mixed": 3125247785,
+        "c3/fp64": 3449972115,
+        "c4/mixed": 38583997906,
+        "c4/fp64": 41032373693,
     },
 }
 
