@@ -52,15 +52,15 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # the kernel sources they were taken on; a changed kernel reports null.
 # Sources: profiles/*_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "d2ebf0b1ed812306880ff7a1f8bba5c0ab937c51e55c715e31663ba77cde723c": {
-        "c1/mixed": 7003834,
-        "c1/fp64": 6927022,
-        "c2/mixed": 43781643922,
-        "c2/fp64": 46690417837,
-        "c3/mixed": 3125247785,
-        "c3/fp64": 3449972115,
-        "c4/mixed": 38583997906,
-        "c4/fp64": 41032373693,
+    "884b657a076854f14a0e246c14a9582c2f68c16695c47408a856b70b7510f855": {
+        "c1/mixed": 7015097,
+        "c1/fp64": 6909634,
+        "c2/mixed": 43782474349,
+        "c2/fp64": 46688779487,
+        "c3/mixed": 3123134395,
+        "c3/fp64": 3448121383,
+        "c4/mixed": 38574833783,
+        "c4/fp64": 41007543211,
     },
 }
 

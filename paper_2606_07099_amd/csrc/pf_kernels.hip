@@ -479,6 +479,45 @@ __device__ __forceinline__ void phase_mismatch(const Sym& m, const Dims& D, St<T
   block_max<S>(mx, bad, scr, tid, nt);
 }
 
+// the same pass for LDS-resident FP64 slices: one bus per thread, its row of
+// Y_bus walked entry by entry (with the FP64 factors' register budget this
+// form issues fewer instructions than the rounds of four entries)
+template <typename T, int S>
+__device__ __forceinline__ void phase_mismatch_lds(const Sym& m, const Dims& D, St<T>& c, int tid, int nt,
+                                                   unsigned char* scr) {
+  double mx = 0.0;
+  int bad = 0;
+  for (int idx = tid; idx < D.n_bus * S; idx += nt) {
+    const int i = idx / S, s = idx % S;
+    double ir = 0.0, ii = 0.0;
+    for (int q = m.y_rp[i]; q < m.y_rp[i + 1]; ++q) {
+      const int j = c.g(m.y_ci[q], s);
+      const double g = m.y_g[q], b = m.y_b[q];
+      ir += g * c.e[j] - b * c.f[j];
+      ii += g * c.f[j] + b * c.e[j];
+    }
+    const int go = c.g(i, s);
+    c.ire[go] = ir;
+    c.iim[go] = ii;
+    const int a = m.bus_blk[i];
+    if (a >= 0) {
+      const double ei = c.e[go], fi = c.f[go];
+      const double P = ei * ir + fi * ii;
+      const double Q = fi * ir - ei * ii;
+      const double F0 = c.ps[idx] - P;
+      const double F1 = m.bus_type[i] == 0 ? c.qs[idx] - Q : 0.0;
+      c.F[sP<S>(i, s)] = F0;
+      c.F[sP<S>(i, s) + 1] = F1;
+      c.y[sP<S>(a, s)] = T(-F0);
+      c.y[sP<S>(a, s) + 1] = T(-F1);
+      bad |= !(isfinite(F0) && isfinite(F1));
+      mx = fmax(mx, fmax(fabs(F0), fabs(F1)));
+    }
+  }
+  __syncthreads();
+  block_max<S>(mx, bad, scr, tid, nt);
+}
+
 // orders this wavefront's earlier global stores before its later loads (HBM
 // state); LDS operations of a wavefront are already in order
 template <bool RES>
@@ -1362,7 +1401,9 @@ __device__ __forceinline__ void rt_bsolve(const Sym& m, const Dims& D, St<T>& c,
 // (with the state in HBM, 1/|V| is formed from e and f: one stream fewer)
 template <typename T, int S, bool RES>
 __device__ __forceinline__ void phase_dv(const Sym& m, const Dims& D, St<T>& c, int tid, int nt) {
-  constexpr int U = 4;
+  // HBM: four items in flight per thread; LDS-resident slices hold fewer
+  // items than threads, and the spare items' loads only cost LDS issue slots
+  constexpr int U = RES ? 1 : 4;
   const int s = tid % S, N = D.n_bus * S;
   for (int base = tid; base < N; base += U * nt) {
     double dth[U], dvm[U], rv[U], e[U], f[U];
@@ -1576,7 +1617,8 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
   constexpr int dx_set = fuse ? 1 : 0, dx_add = fuse ? 2 : 0;
   pc.mark(PH_SETUP);
   while (true) {
-    phase_mismatch<T, S>(m, D, c, tid, nt, scr);
+    if constexpr (RES && sizeof(T) == 8) phase_mismatch_lds<T, S>(m, D, c, tid, nt, scr);
+    else phase_mismatch<T, S>(m, D, c, tid, nt, scr);
     pc.mark(PH_MISMATCH);
     for (int s = 0; s < S; ++s) {
       if (!((act >> s) & 1)) continue;
