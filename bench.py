@@ -52,15 +52,15 @@ KERNEL_SOURCES = ("paper_2606_07099_amd/csrc/pf_kernels.hip", "paper_2606_07099_
 # the kernel sources they were taken on; a changed kernel reports null.
 # Sources: profiles/*_hbm_counters.md
 MEASURED_TRAFFIC = {
-    "884b657a076854f14a0e246c14a9582c2f68c16695c47408a856b70b7510f855": {
-        "c1/mixed": 7015097,
-        "c1/fp64": 6909634,
-        "c2/mixed": 43782474349,
-        "c2/fp64": 46688779487,
-        "c3/mixed": 3123134395,
-        "c3/fp64": 3448121383,
-        "c4/mixed": 38574833783,
-        "c4/fp64": 41007543211,
+    "0e9949f99c6bfeb39010a3811daa701dedba881ec271c092c0951986c17ab1d1": {
+        "c1/mixed": 7003853,
+        "c1/fp64": 6899376,
+        "c2/mixed": 43249094750,
+        "c2/fp64": 46121311935,
+        "c3/mixed": 2992607351,
+        "c3/fp64": 3339025927,
+        "c4/mixed": 37813363924,
+        "c4/fp64": 39909501093,
     },
 }
 

@@ -254,6 +254,17 @@ __device__ __forceinline__ void fill_gather(const Sym& m, const St<T>& c, int s,
 
 // 1/sqrt(x) for x > 0 to a few units in the last place: the hardware
 // estimate refined by two Newton steps
+// sin and cos of an FP64 angle behind a call boundary: inlined into the
+// 1024-thread Newton kernel (128 registers per lane), the polynomial's
+// constants were hoisted to the kernel's start, spilled, and reloaded one by
+// one from scratch for every item of the state update; inside a call they are
+// formed where they are used (one value reloaded per item instead of nine)
+__device__ __attribute__((noinline)) double2 sincos_call(double x) {
+  double sn, cs;
+  sincos(x, &sn, &cs);
+  return make_double2(sn, cs);
+}
+
 __device__ __forceinline__ double rsqrt_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
   y = y * (1.5 - 0.5 * x * y * y);
@@ -1750,7 +1761,13 @@ __global__ void __launch_bounds__(RES ? res_newton_threads<T>() : 1024) k_newton
         c.vm[o] = vm;
       }
       double sn, cs;
-      sincos(va, &sn, &cs);
+      if (RES) {
+        sincos(va, &sn, &cs);
+      } else {
+        const double2 r = sincos_call(va);
+        sn = r.x;
+        cs = r.y;
+      }
       c.e[o] = vm * cs;
       c.f[o] = vm * sn;
       if (RES) c.rvm[o] = 1.0 / vm;
